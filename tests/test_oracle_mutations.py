@@ -1,0 +1,97 @@
+"""Plant plausible mistakes in copies of the oracle's C source and check that
+the pins catch every one (a pin that cannot fail pins nothing).  Mistakes are
+planted in the oracle only, on the CPU."""
+import os
+import tempfile
+
+import pytest
+
+import oracle
+import oracle_pins
+
+# (name, function whose body is edited, old text, new text)
+MUTATIONS = [
+    ("p2m log sign", "orc_p2m", "a[k] -= mj * pw / (double)k;", "a[k] += mj * pw / (double)k;"),
+    ("p2m harmonic power off by one", "orc_p2m", "{ a[k] += mj * pw; pw *= d; }", "{ pw *= d; a[k] += mj * pw; }"),
+    ("m2m dropped a0 term", "orc_m2m", "cplx s = -a[0] * rp[l] / (double)l;", "cplx s = 0;"),
+    ("m2m binomial index", "orc_m2m", "binom(l - 1, k - 1)", "binom(l, k - 1)"),
+    ("m2m shift direction", "orc_m2m", "cplx r = rx + I * ry;", "cplx r = -(rx + I * ry);"),
+    ("m2l alternating sign", "orc_m2l", "double sgn = (l & 1) ? -1.0 : 1.0;", "double sgn = 1.0;"),
+    ("m2l binomial index", "orc_m2l", "binom(k + l - 1, l)", "binom(k + l, l)"),
+    ("m2l log term sign", "orc_m2l", "cplx s0 = a[0] * clog(rho);", "cplx s0 = -a[0] * clog(rho);"),
+    ("m2l a0/l term", "orc_m2l", "cplx s = -a[0] / (double)l;", "cplx s = 0;"),
+    ("l2l binomial", "orc_l2l", "binom(j, l)", "binom(j + 1, l)"),
+    ("l2l shift direction", "orc_l2l", "cplx r = rx + I * ry;", "cplx r = -(rx + I * ry);"),
+    ("local derivative weight", "orc_eval_local", "(double)(l + 1) * b[l + 1]", "(double)l * b[l + 1]"),
+    ("median rank", "split_set", "keyed piv = kv[n / 2];", "keyed piv = kv[(n + 1) / 2];"),
+    ("split axis rule", "split_set", "(r[1] - r[0] >= r[3] - r[2]) ? 0 : 1", "(r[1] - r[0] >= r[3] - r[2]) ? 1 : 0"),
+    ("target split side", "split_set", "lo[k] = !(tgt[2 * t[k] + ax] >= piv.c);", "lo[k] = !(tgt[2 * t[k] + ax] > piv.c);"),
+    ("radius definition", "orc_build", "T->rad[g] = 0.5 * sqrt(w * w + h * h);", "T->rad[g] = sqrt(w * w + h * h);"),
+    ("child numbering", "orc_build", "ss2[2 * j] = ss[j]; ss2[2 * j + 1] = ss[j] + nlo;",
+     "ss2[2 * j + 1] = ss[j]; ss2[2 * j] = ss[j] + nlo;"),
+    ("theta test uses max for both", "theta_weak", "double r = rb >= rs ? rs : rb;", "double r = rb >= rs ? rb : rs;"),
+    ("lists: candidates from weak", "orc_build", "for (int64_t e = T->soff[l - 1][q]; e < T->soff[l - 1][q + 1]; ++e) {\n                int64_t s = T->sidx[l - 1][e];",
+     "for (int64_t e = T->woff[l - 1][q]; e < T->woff[l - 1][q + 1]; ++e) {\n                int64_t s = T->widx[l - 1][e];"),
+    ("l2l source level", "orc_eval", "int64_t g = box_off(l) + b, q = box_off(l - 1) + b / 4;",
+     "int64_t g = box_off(l) + b, q = box_off(l - 1) + (b / 4 + 1) % nbox(l - 1);"),
+    ("p2p coincident rule", "orc_eval", "if (xx == yx && xy == yy) continue;\n                    cplx w = (yx - xx) + I * (yy - xy);\n                    cplx mj",
+     "if (xx == yx) continue;\n                    cplx w = (yx - xx) + I * (yy - xy);\n                    cplx mj"),
+    ("direct sum drops imaginary part of m", "orc_direct", "cplx mj = m[2 * j] + I * m[2 * j + 1];", "cplx mj = m[2 * j];"),
+    ("level rule off by one", "orc_nlevels", "while (lhs < (__int128)5 * n)", "while (lhs <= (__int128)5 * n)"),
+]
+
+
+def _mutate(src, func, old, new):
+    start = src.index(func + "(")
+    # the definition, not a forward declaration or a call: first '{' after it
+    body = src.index("{", start)
+    end = src.index("\n}\n", body)
+    seg = src[start:end]
+    assert seg.count(old) >= 1, "mutation anchor not found in %s: %r" % (func, old)
+    return src[:start] + seg.replace(old, new, 1) + src[end:]
+
+
+@pytest.fixture(scope="module")
+def variants(orc):
+    src = oracle.source_text()
+    d = tempfile.mkdtemp(prefix="orc_mut_")
+    out = []
+    for k, (name, func, old, new) in enumerate(MUTATIONS):
+        text = _mutate(src, func, old, new)
+        so = oracle.compile_variant(text, os.path.join(d, "mut%02d.so" % k))
+        out.append((name, so))
+    return out
+
+
+_RUNNER = r"""
+import sys
+sys.path[:0] = [%r, %r]
+import oracle, oracle_pins
+with oracle.variant(%r):
+    for pin in oracle_pins.ALL_PINS:
+        try:
+            pin(oracle)
+        except Exception as e:
+            print("caught by", pin.__name__, type(e).__name__)
+            sys.exit(3)
+print("not caught")
+sys.exit(0)
+"""
+
+
+def _caught(so):
+    """Run every pin on the variant in a child process (a planted mistake may
+    also crash the variant, which then counts as caught)."""
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = _RUNNER % (os.path.dirname(here), here, so)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    return r.returncode != 0, (r.stdout + r.stderr)[-400:]
+
+
+@pytest.mark.parametrize("k", range(len(MUTATIONS)), ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(variants, k):
+    name, so = variants[k]
+    caught, log = _caught(so)
+    assert caught, "no pin catches the planted mistake: %s\n%s" % (name, log)
