@@ -1,0 +1,106 @@
+// Internal declarations of the gfx950 FMM library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "fmm2d.h"
+
+#define FMM_PMAX 64             // largest expansion order supported
+#define FMM_BN 132              // binomial table: C(n,k) for 0 <= n,k < FMM_BN
+#define FMM_MAXL 15             // deepest tree (4^15 leaves)
+#define FMM_DEFAULT_LIST_CAP 256
+
+// status bits written by kernels into the handle's device status word
+#define FMM_ST_LIST_OVERFLOW 1
+
+static inline int64_t box_off(int l) { return ((((int64_t)1) << (2 * l)) - 1) / 3; }
+static inline int64_t nbox(int l) { return ((int64_t)1) << (2 * l); }
+static inline int64_t start_off(int l) { return box_off(l) + l; }
+
+__device__ __forceinline__ int64_t d_box_off(int l) { return ((((int64_t)1) << (2 * l)) - 1) / 3; }
+__device__ __forceinline__ int64_t d_start_off(int l) { return d_box_off(l) + l; }
+
+// --------------------------------------------------------------------------
+// Workspace layout: every array of one evaluation, carved out of the caller's
+// buffer at 256-byte aligned offsets.  The layout depends only on the sizes
+// and options, so fmm2d_workspace_size and fmm2d_eval agree.
+struct fmm_layout {
+    int64_t ns, nt;    // sources; separate targets (0 = at sources)
+    int L, p, cap;     // levels, order, list capacity per box
+    int mixed, learned;
+    int64_t nb;        // boxes over all levels
+    int64_t nleaf;
+    int64_t nstart;    // entries of the per-level start arrays
+    int64_t nstep;     // entries of the per-split-step start arrays
+    int64_t listcap;   // entries of each global list array
+    // offsets (bytes)
+    size_t keys[2], vals[2];     // radix sort ping-pong (max(ns,nt) each)
+    size_t hist;                 // radix histogram / scan block sums
+    size_t sl[1];                // source lists: 6 x ns int32 (lx, ly, li + partition outputs)
+    size_t tl[1];                // target lists: 6 x nt int32
+    size_t sside, tside;         // side flag per original index
+    size_t bsum;                 // partition block sums (6 lists)
+    size_t sstep, tstep;         // per-step starts (sources / targets)
+    size_t seg_axis, seg_nlo, seg_tlo, seg_LO, seg_TLO;
+    size_t sstart, tstart;       // per-level starts (output)
+    size_t centre, radius;
+    size_t wcnt, scnt;           // per-box list counts (current level)
+    size_t woff, soff;           // per-level list offsets
+    size_t widx, sidx;           // global list arrays
+    size_t lbsum;                // list scan block sums
+    size_t srcs;                 // double4 sources in leaf order
+    size_t tgts;                 // double2 targets in leaf order
+    size_t m32;                  // float2 strengths in leaf order (mixed)
+    size_t A, B;                 // FP64 multipoles / locals [nb][p+1] complex
+    size_t A32;                  // FP32 radius-scaled multipoles (mixed)
+    size_t feat, porder, pbucket;// learned order: features, orders, bucketed pairs
+    size_t pairs;                // M2L pair table (target, source) for bucketing
+    size_t total;
+};
+
+int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, int learned,
+                    fmm_layout *lay);
+
+// --------------------------------------------------------------------------
+// Launchers (defined in the .hip files).  All asynchronous on `st`.
+struct fmm_tree_args {
+    int64_t ns, nt;               // nt = 0 at sources
+    int L;
+    double theta;
+    const double *src;            // [2 ns] caller order
+    const double *tgt;            // [2 nt] or NULL
+    char *ws;
+    const fmm_layout *lay;
+    int32_t *status;              // device status word
+    int cap;
+};
+// Builds perm/tperm, per-level starts, centres, radii and lists; gathers the
+// sources (with strengths) and targets into leaf order.
+hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t st);
+hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st);
+
+struct fmm_eval_args {
+    int L, p, kernel, mixed;
+    int64_t ns, nt;               // nt == ns when at sources
+    int at_sources;
+    const char *ws;
+    const fmm_layout *lay;
+    const double *binom;          // [FMM_BN][FMM_BN] FP64
+    int32_t cap;
+};
+hipError_t fmm_p2m(const fmm_eval_args &a, hipStream_t st);
+hipError_t fmm_m2m(const fmm_eval_args &a, hipStream_t st);
+hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st);
+hipError_t fmm_l2l(const fmm_eval_args &a, hipStream_t st);
+hipError_t fmm_p2p_l2p(const fmm_eval_args &a, double *phi, double *dphi, hipStream_t st);
+
+hipError_t fmm_direct(int64_t ns, const double *src, const double *m, int64_t nt,
+                      const double *tgt, const int64_t *tsel, int64_t nsel, int kernel,
+                      double *phi, double *dphi, hipStream_t st);
+
+// device-wide exclusive scan of int32 (n entries) into out[0..n]; out[n] is
+// the total; base (device, may be NULL) is added to every entry.
+hipError_t fmm_scan_i32(const int32_t *in, int32_t *out, int64_t n, const int32_t *base,
+                        int32_t *blocksums, hipStream_t st);
+__host__ __device__ int64_t fmm_scan_blocks(int64_t n);

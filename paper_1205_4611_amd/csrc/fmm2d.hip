@@ -1,0 +1,420 @@
+// Host side of the C ABI (include/fmm2d.h): argument checks, workspace
+// layout, and the order of the device phases of one evaluation.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "common.h"
+
+struct fmm2d_handle {
+    int device;
+    char err[512];
+    int32_t *d_status;      // device status word
+    double *d_binom;        // [FMM_BN][FMM_BN]
+    hipEvent_t ev[FMM2D_NPHASE + 1];
+    int timing_valid;
+    hipStream_t last_stream;
+    // last evaluation
+    int have_topo;
+    fmm_layout lay;
+    const char *ws;
+    int64_t ns, nt;
+    int L, p, at_sources, used_model;
+};
+
+static int fail(fmm2d_handle *h, int code, const char *fmt, ...)
+{
+    if (h) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(h->err, sizeof(h->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(h, x)                                                                          \
+    do {                                                                                      \
+        hipError_t e__ = (x);                                                                 \
+        if (e__ != hipSuccess)                                                                \
+            return fail((h), FMM2D_EHIP, "%s: %s (%s:%d)", #x, hipGetErrorString(e__), __FILE__, \
+                        __LINE__);                                                            \
+    } while (0)
+
+extern "C" void fmm2d_default_opts(fmm2d_opts *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->theta = 0.5;
+    o->tol = 1e-6;
+    o->p = 0;
+    o->levels = -1;
+    o->leaf_target = 45;
+    o->kernel = FMM2D_KERNEL_LOG;
+    o->precision = FMM2D_FP64;
+    o->porder = FMM2D_P_FIXED;
+    o->flags = 0;
+    o->list_cap = 0;
+}
+
+// eq. (Nlevels): the smallest L >= 0 with 8 nd 4^L >= 5 n (exact integers).
+extern "C" int fmm2d_nlevels(int64_t n, int32_t nd)
+{
+    if (n <= 0 || nd <= 0) return -1;
+    int L = 0;
+    __int128 lhs = (__int128)8 * nd;
+    while (lhs < (__int128)5 * n) {
+        lhs *= 4;
+        ++L;
+    }
+    return L;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, int learned,
+                    fmm_layout *lay)
+{
+    memset(lay, 0, sizeof(*lay));
+    lay->ns = ns; lay->nt = nt; lay->L = L; lay->p = p; lay->cap = cap;
+    lay->mixed = mixed; lay->learned = learned;
+    lay->nb = box_off(L + 1);
+    lay->nleaf = nbox(L);
+    lay->nstart = start_off(L + 1);
+    lay->nstep = (((int64_t)1) << (2 * L + 1)) + 2 * L + 2;
+    lay->listcap = (int64_t)cap * lay->nb + 4;
+    const int64_t nmax = ns > nt ? ns : nt;
+    const int64_t P1 = p + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + (bytes ? bytes : 1)); return r; };
+    const int64_t rs_blocks = (nmax + 4095) / 4096;
+    const int64_t hist_n = 256 * rs_blocks + 1;
+    const int64_t seg_scan_n = fmm_scan_blocks(lay->nleaf + 1) + 1;
+    lay->keys[0] = take(8 * nmax);
+    lay->keys[1] = take(8 * nmax);
+    lay->vals[0] = take(4 * nmax);
+    lay->vals[1] = take(4 * nmax);
+    lay->hist = take(4 * (hist_n > seg_scan_n ? hist_n : seg_scan_n));
+    {
+        int64_t a = fmm_scan_blocks(hist_n) + 1;
+        int64_t b = 6 * (fmm_scan_blocks(nmax) + 1);
+        lay->bsum = take(4 * (a > b ? a : b));
+    }
+    lay->sl[0] = take(4 * 6 * ns);
+    lay->tl[0] = take(4 * 6 * nt);
+    lay->sside = take(ns);
+    lay->tside = take(nt);
+    lay->sstep = take(4 * lay->nstep);
+    lay->tstep = take(4 * lay->nstep);
+    lay->seg_axis = take(lay->nleaf + 1);
+    lay->seg_nlo = take(4 * (lay->nleaf + 1));
+    lay->seg_tlo = take(4 * (lay->nleaf + 1));
+    lay->seg_LO = take(4 * (lay->nleaf + 2));
+    lay->seg_TLO = take(4 * (lay->nleaf + 2));
+    lay->sstart = take(4 * lay->nstart);
+    lay->tstart = take(4 * lay->nstart);
+    lay->centre = take(16 * lay->nb);
+    lay->radius = take(8 * lay->nb);
+    lay->wcnt = take(4 * lay->nleaf);
+    lay->scnt = take(4 * lay->nleaf);
+    lay->woff = take(4 * lay->nstart);
+    lay->soff = take(4 * lay->nstart);
+    lay->widx = take(4 * lay->listcap);
+    lay->sidx = take(4 * lay->listcap);
+    lay->lbsum = take(4 * (fmm_scan_blocks(lay->nleaf) + 2));
+    lay->srcs = take(32 * ns);
+    lay->tgts = take(16 * nt);
+    lay->m32 = mixed ? take(8 * ns) : 0;
+    lay->A = take(16 * lay->nb * P1);
+    lay->B = take(16 * lay->nb * P1);
+    lay->A32 = mixed ? take(8 * lay->nb * P1) : 0;
+    lay->total = o;
+    return 0;
+}
+
+extern "C" int fmm2d_create(fmm2d_handle **out, int device)
+{
+    if (!out) return FMM2D_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FMM2D_EINVAL;
+    fmm2d_handle *h = (fmm2d_handle *)calloc(1, sizeof(fmm2d_handle));
+    if (!h) return FMM2D_EINVAL;
+    h->device = device;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc((void **)&h->d_status, 64);
+    if (e == hipSuccess) e = hipMemset(h->d_status, 0, 64);
+    if (e == hipSuccess) e = hipMalloc((void **)&h->d_binom, sizeof(double) * FMM_BN * FMM_BN);
+    if (e == hipSuccess) {
+        // Pascal's rule in FP64 (exact below 2^53)
+        double *t = (double *)calloc(FMM_BN * FMM_BN, sizeof(double));
+        for (int n = 0; n < FMM_BN; ++n) {
+            t[n * FMM_BN] = 1.0;
+            for (int k = 1; k <= n; ++k)
+                t[n * FMM_BN + k] = t[(n - 1) * FMM_BN + k - 1] + (k < n ? t[(n - 1) * FMM_BN + k] : 0.0);
+        }
+        e = hipMemcpy(h->d_binom, t, sizeof(double) * FMM_BN * FMM_BN, hipMemcpyHostToDevice);
+        free(t);
+    }
+    for (int i = 0; i <= FMM2D_NPHASE && e == hipSuccess; ++i) e = hipEventCreate(&h->ev[i]);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        fmm2d_destroy(h);
+        return FMM2D_EHIP;
+    }
+    *out = h;
+    return FMM2D_OK;
+}
+
+extern "C" void fmm2d_destroy(fmm2d_handle *h)
+{
+    if (!h) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(h->device);
+    for (int i = 0; i <= FMM2D_NPHASE; ++i)
+        if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+    if (h->d_status) (void)hipFree(h->d_status);
+    if (h->d_binom) (void)hipFree(h->d_binom);
+    (void)hipSetDevice(prev);
+    free(h);
+}
+
+extern "C" const char *fmm2d_last_error(const fmm2d_handle *h) { return h ? h->err : "null handle"; }
+
+// Resolve levels and order from opts; returns 0 or an error code.
+static int resolve(fmm2d_handle *h, int64_t ns, const fmm2d_opts *o, int *L, int *p, int *cap)
+{
+    if (!o) return fail(h, FMM2D_EINVAL, "opts is NULL");
+    if (ns < 1 || ns > ((int64_t)1 << 30)) return fail(h, FMM2D_EINVAL, "n_src must be in [1, 2^30]");
+    if (!(o->theta > 0.0 && o->theta < 1.0)) return fail(h, FMM2D_EINVAL, "theta must be in (0,1)");
+    if (o->kernel != FMM2D_KERNEL_LOG && o->kernel != FMM2D_KERNEL_HARMONIC)
+        return fail(h, FMM2D_EINVAL, "unknown kernel %u", o->kernel);
+    if (o->precision != FMM2D_FP64 && o->precision != FMM2D_MIXED)
+        return fail(h, FMM2D_EINVAL, "unknown precision %u", o->precision);
+    if (o->porder != FMM2D_P_FIXED && o->porder != FMM2D_P_LEARNED)
+        return fail(h, FMM2D_EINVAL, "unknown order policy %u", o->porder);
+    int pp = o->p;
+    if (pp == 0) {
+        if (!(o->tol > 0.0 && o->tol < 1.0)) return fail(h, FMM2D_EINVAL, "tol must be in (0,1)");
+        pp = (int)ceil(log(o->tol) / log(o->theta));
+    }
+    if (pp < 1 || pp > FMM_PMAX) return fail(h, FMM2D_EINVAL, "p=%d outside 1..%d", pp, FMM_PMAX);
+    int LL = o->levels;
+    if (LL < 0) {
+        if (o->leaf_target < 1) return fail(h, FMM2D_EINVAL, "leaf_target must be >= 1");
+        LL = fmm2d_nlevels(ns, o->leaf_target);
+    }
+    if (LL > FMM_MAXL) return fail(h, FMM2D_EINVAL, "levels=%d > %d", LL, FMM_MAXL);
+    if (nbox(LL) > ns) return fail(h, FMM2D_EINVAL, "4^L = %lld exceeds n_src = %lld", (long long)nbox(LL), (long long)ns);
+    int c = o->list_cap > 0 ? o->list_cap : FMM_DEFAULT_LIST_CAP;
+    *L = LL;
+    *p = pp;
+    *cap = c;
+    return 0;
+}
+
+extern "C" int fmm2d_workspace_size(fmm2d_handle *h, int64_t n_src, int64_t n_tgt, const fmm2d_opts *opts,
+                                    size_t *bytes)
+{
+    if (!h || !bytes) return fail(h, FMM2D_EINVAL, "NULL argument");
+    int L, p, cap;
+    int rc = resolve(h, n_src, opts, &L, &p, &cap);
+    if (rc) return rc;
+    if (n_tgt < 0 || n_tgt > ((int64_t)1 << 30)) return fail(h, FMM2D_EINVAL, "n_tgt out of range");
+    fmm_layout lay;
+    fmm_plan_layout(n_src, n_tgt, L, p, cap, opts->precision == FMM2D_MIXED, opts->porder == FMM2D_P_LEARNED,
+                    &lay);
+    *bytes = lay.total;
+    return FMM2D_OK;
+}
+
+__global__ void k_zero_status(int32_t *s) { s[threadIdx.x] = 0; }
+
+extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, const double *m, int64_t n_tgt,
+                          const double *tgt, const fmm2d_opts *opts, double *phi, double *dphi, void *ws,
+                          size_t ws_bytes, void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    h->err[0] = 0;
+    int L, p, cap;
+    int rc = resolve(h, n_src, opts, &L, &p, &cap);
+    if (rc) return rc;
+    if (!src || !m || !ws) return fail(h, FMM2D_EINVAL, "src, m and ws must be non-NULL");
+    const bool LOG = opts->kernel == FMM2D_KERNEL_LOG;
+    if (!dphi && !(LOG && phi)) return fail(h, FMM2D_EINVAL, "no output requested");
+    const int64_t nt = tgt ? n_tgt : 0;
+    if (tgt && (n_tgt < 1 || n_tgt > ((int64_t)1 << 30))) return fail(h, FMM2D_EINVAL, "n_tgt out of range");
+    const int mixed = opts->precision == FMM2D_MIXED;
+    const int learned = opts->porder == FMM2D_P_LEARNED;
+    if (learned && (opts->flags & FMM2D_FLAG_REQUIRE_MODEL))
+        return fail(h, FMM2D_ENOMODEL, "learned order requested but no model is loaded");
+    fmm_layout lay;
+    fmm_plan_layout(n_src, nt, L, p, cap, mixed, learned, &lay);
+    if (ws_bytes < lay.total)
+        return fail(h, FMM2D_ENOSPC, "workspace of %zu bytes < %zu needed", ws_bytes, lay.total);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(h, hipSetDevice(h->device));
+    const bool timing = (opts->flags & FMM2D_FLAG_TIMING) != 0;
+    k_zero_status<<<1, 16, 0, st>>>(h->d_status);
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[0], st));
+
+    char *w = (char *)ws;
+    fmm_tree_args ta;
+    ta.ns = n_src; ta.nt = nt; ta.L = L; ta.theta = opts->theta;
+    ta.src = src; ta.tgt = tgt; ta.ws = w; ta.lay = &lay; ta.status = h->d_status; ta.cap = cap;
+    HIPCHK(h, fmm_build_tree(ta, m, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_TREE], st));
+    HIPCHK(h, fmm_build_lists(ta, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_LISTS], st));
+
+    fmm_eval_args ea;
+    ea.L = L; ea.p = p; ea.kernel = (int)opts->kernel; ea.mixed = mixed;
+    ea.ns = n_src; ea.nt = nt ? nt : n_src; ea.at_sources = nt == 0;
+    ea.ws = w; ea.lay = &lay; ea.binom = h->d_binom; ea.cap = cap;
+    HIPCHK(h, fmm_p2m(ea, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], st));
+    HIPCHK(h, fmm_m2m(ea, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2M], st));
+    // learned order inference would run here
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_PORDER], st));
+    HIPCHK(h, fmm_m2l(ea, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2L], st));
+    HIPCHK(h, fmm_l2l(ea, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_L2L], st));
+    HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2P], st));
+
+    h->timing_valid = timing;
+    h->last_stream = st;
+    h->have_topo = 1;
+    h->lay = lay;
+    h->ws = w;
+    h->ns = n_src;
+    h->nt = nt;
+    h->L = L;
+    h->p = p;
+    h->at_sources = nt == 0;
+    h->used_model = 0;
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_direct(fmm2d_handle *h, int64_t n_src, const double *src, const double *m, int64_t n_tgt,
+                            const double *tgt, const int64_t *tsel, int64_t n_sel, uint32_t kernel, double *phi,
+                            double *dphi, void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    if (n_src < 1 || !src || !m) return fail(h, FMM2D_EINVAL, "bad sources");
+    if (kernel != FMM2D_KERNEL_LOG && kernel != FMM2D_KERNEL_HARMONIC) return fail(h, FMM2D_EINVAL, "bad kernel");
+    if (!tgt) { tgt = src; n_tgt = n_src; }
+    if (n_tgt < 1) return fail(h, FMM2D_EINVAL, "bad n_tgt");
+    if (tsel && n_sel < 0) return fail(h, FMM2D_EINVAL, "bad n_sel");
+    if (!dphi && !(kernel == FMM2D_KERNEL_LOG && phi)) return fail(h, FMM2D_EINVAL, "no output requested");
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, fmm_direct(n_src, src, m, n_tgt, tgt, tsel, n_sel, (int)kernel, phi, dphi, (hipStream_t)stream));
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_sync(fmm2d_handle *h, void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, hipStreamSynchronize((hipStream_t)stream));
+    int32_t s = 0;
+    HIPCHK(h, hipMemcpy(&s, h->d_status, sizeof(s), hipMemcpyDeviceToHost));
+    if (s & FMM_ST_LIST_OVERFLOW)
+        return fail(h, FMM2D_ENOSPC, "interaction lists overflowed list_cap; raise fmm2d_opts.list_cap");
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_get_topology(fmm2d_handle *h, fmm2d_topology *t)
+{
+    if (!h || !t) return FMM2D_EINVAL;
+    if (!h->have_topo) return fail(h, FMM2D_EINVAL, "no evaluation yet");
+    const fmm_layout &lay = h->lay;
+    const char *w = h->ws;
+    memset(t, 0, sizeof(*t));
+    t->levels = h->L;
+    t->p = h->p;
+    t->n_src = h->ns;
+    t->n_tgt = h->at_sources ? h->ns : h->nt;
+    t->perm = reinterpret_cast<const int32_t *>(w + lay.sl[0]) + 2 * h->ns;
+    t->tperm = h->at_sources ? t->perm : reinterpret_cast<const int32_t *>(w + lay.tl[0]) + 2 * h->nt;
+    t->sstart = reinterpret_cast<const int32_t *>(w + lay.sstart);
+    t->tstart = h->at_sources ? t->sstart : reinterpret_cast<const int32_t *>(w + lay.tstart);
+    t->centre = reinterpret_cast<const double *>(w + lay.centre);
+    t->radius = reinterpret_cast<const double *>(w + lay.radius);
+    t->weak_off = reinterpret_cast<const int32_t *>(w + lay.woff);
+    t->weak_idx = reinterpret_cast<const int32_t *>(w + lay.widx);
+    t->strong_off = reinterpret_cast<const int32_t *>(w + lay.soff);
+    t->strong_idx = reinterpret_cast<const int32_t *>(w + lay.sidx);
+    t->mpole = reinterpret_cast<const double *>(w + lay.A);
+    t->local = reinterpret_cast<const double *>(w + lay.B);
+    t->porder = nullptr;
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_get_stats(fmm2d_handle *h, fmm2d_stats *s)
+{
+    if (!h || !s) return FMM2D_EINVAL;
+    memset(s, 0, sizeof(*s));
+    for (int i = 0; i < FMM2D_NPHASE; ++i) s->ms[i] = -1.0f;
+    if (!h->have_topo) return fail(h, FMM2D_EINVAL, "no evaluation yet");
+    s->status = fmm2d_sync(h, h->last_stream);
+    if (h->timing_valid) {
+        for (int i = 0; i < FMM2D_NPHASE; ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) s->ms[i] = ms;
+        }
+    }
+    const fmm_layout &lay = h->lay;
+    const int L = h->L;
+    // list totals and the P2P pair count, from the device lists
+    int32_t wend = 0, send_prev = 0, send = 0;
+    const int32_t *woff = reinterpret_cast<const int32_t *>(h->ws + lay.woff);
+    const int32_t *soff = reinterpret_cast<const int32_t *>(h->ws + lay.soff);
+    HIPCHK(h, hipMemcpy(&wend, woff + start_off(L) + nbox(L), 4, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(&send, soff + start_off(L) + nbox(L), 4, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(&send_prev, soff + start_off(L), 4, hipMemcpyDeviceToHost));
+    s->n_weak = wend;
+    s->n_strong = (int64_t)send - send_prev;
+    if (s->status == FMM2D_OK) {
+        const int64_t nl = nbox(L);
+        int32_t *so = (int32_t *)malloc(4 * (nl + 1));
+        int32_t *ss = (int32_t *)malloc(4 * (nl + 1));
+        int32_t *ts = (int32_t *)malloc(4 * (nl + 1));
+        int32_t *si = (int32_t *)malloc(4 * (s->n_strong + 1));
+        const char *w = h->ws;
+        hipError_t e = hipMemcpy(so, soff + start_off(L), 4 * (nl + 1), hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMemcpy(ss, reinterpret_cast<const int32_t *>(w + lay.sstart) + start_off(L), 4 * (nl + 1),
+                          hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMemcpy(ts,
+                          reinterpret_cast<const int32_t *>(w + (h->at_sources ? lay.sstart : lay.tstart)) + start_off(L),
+                          4 * (nl + 1), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && s->n_strong > 0)
+            e = hipMemcpy(si, reinterpret_cast<const int32_t *>(w + lay.sidx) + send_prev, 4 * s->n_strong,
+                          hipMemcpyDeviceToHost);
+        if (e == hipSuccess) {
+            int64_t pairs = 0;
+            for (int64_t t = 0; t < nl; ++t) {
+                int64_t nsrc = 0;
+                for (int32_t k = so[t]; k < so[t + 1]; ++k) {
+                    int32_t b = si[k - send_prev];
+                    nsrc += ss[b + 1] - ss[b];
+                }
+                pairs += nsrc * (ts[t + 1] - ts[t]);
+            }
+            s->n_p2p_pairs = pairs;
+        }
+        free(so); free(ss); free(ts); free(si);
+        HIPCHK(h, e);
+    }
+    s->used_model = h->used_model;
+    return FMM2D_OK;
+}

@@ -1,0 +1,685 @@
+// Topological phase on gfx950: presort, equal-count median splits, box
+// geometry and theta-criterion interaction lists (Goude & Engblom, Sec. 2 and
+// Sec. 3.2).  Integer work plus FP64 compares; this file is compiled with
+// -ffp-contract=off so the geometry and theta-tests round exactly as written.
+//
+// Design (replaces the paper's warp-32 pivot search, Alg. "Partitioning with
+// successive splits", which is non-deterministic across blocks):
+//  * each point set is kept as three index lists per segment: sorted by
+//    (x, index), sorted by (y, index), and in index order.  A stable LSD radix
+//    sort of the order-preserving 64-bit key of each coordinate builds the
+//    first two once.
+//  * one split of every segment is then data-parallel: the median is the
+//    element at rank floor(n/2) of the axis list, and every list is stably
+//    partitioned by the resulting side flag (one scan per list).  Stable
+//    partitions keep each list sorted inside every segment, so the rectangles
+//    of the next step come from the segment ends.
+//  * the tree is a pyramid with children 4b..4b+3, so segment j of split step
+//    k becomes segments 2j, 2j+1 of step k+1 and no host round-trip is needed.
+#pragma clang fp contract(off)
+
+#include "common.h"
+
+#define WAVE 64
+
+// ---------------------------------------------------------------- scans --
+#define SCAN_T 256
+#define SCAN_I 8
+#define SCAN_B (SCAN_T * SCAN_I)
+
+__host__ __device__ int64_t fmm_scan_blocks(int64_t n) { return (n + SCAN_B - 1) / SCAN_B; }
+
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int32_t t = __shfl_up(v, o, WAVE);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over the block; *total = block sum.
+// sh must hold blockDim.x/64 ints.
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *sh, int32_t *total)
+{
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    int32_t inc = wave_incl_scan(v);
+    if (lane == WAVE - 1) sh[w] = inc;
+    __syncthreads();
+    int32_t off = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        int32_t s = sh[i];
+        off += (i < w) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t *__restrict__ in, int64_t n,
+                                                         int32_t *__restrict__ bs)
+{
+    __shared__ int32_t sh[SCAN_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_I; ++i)
+        if (base + i < n) s += in[base + i];
+    int32_t tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) bs[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of the block sums in place (+ *base), writes
+// the grand total to bs[nb] and, if out_total, to *out_total.
+__global__ void __launch_bounds__(1024) k_scan_sums(int32_t *__restrict__ bs, int64_t nb,
+                                                     const int32_t *__restrict__ base,
+                                                     int32_t *__restrict__ out_total)
+{
+    __shared__ int32_t sh[1024 / WAVE];
+    int32_t carry = base ? *base : 0;
+    for (int64_t c = 0; c < nb; c += blockDim.x) {
+        int64_t k = c + threadIdx.x;
+        int32_t v = k < nb ? bs[k] : 0;
+        int32_t tot;
+        int32_t ex = block_excl_scan(v, sh, &tot);
+        if (k < nb) bs[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        bs[nb] = carry;
+        if (out_total) *out_total = carry;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_down(const int32_t *__restrict__ in,
+                                                       int32_t *__restrict__ out, int64_t n,
+                                                       const int32_t *__restrict__ bs)
+{
+    __shared__ int32_t sh[SCAN_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
+    int32_t v[SCAN_I];
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_I; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        s += v[i];
+    }
+    int32_t tot;
+    int32_t run = block_excl_scan(s, sh, &tot) + bs[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SCAN_I; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+}
+
+hipError_t fmm_scan_i32(const int32_t *in, int32_t *out, int64_t n, const int32_t *base,
+                        int32_t *blocksums, hipStream_t st)
+{
+    int64_t nb = fmm_scan_blocks(n);
+    if (nb > 0) k_scan_reduce<<<(unsigned)nb, SCAN_T, 0, st>>>(in, n, blocksums);
+    k_scan_sums<<<1, 1024, 0, st>>>(blocksums, nb, base, out + n);
+    if (nb > 0) k_scan_down<<<(unsigned)nb, SCAN_T, 0, st>>>(in, out, n, blocksums);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- radix presort --
+// Stable LSD radix sort of (64-bit key, int32 value), 8-bit digits.  Starting
+// from the identity order, equal keys stay in index order, which is exactly
+// the (coordinate, index) order the split rule asks for.
+#define RS_T 256
+#define RS_TILES 16
+#define RS_BLOCK (RS_T * RS_TILES)
+
+__device__ __forceinline__ uint64_t order_key(double x)
+{
+    if (x == 0.0) x = 0.0; // -0 and +0 compare equal: give them one key
+    uint64_t u = (uint64_t)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__global__ void k_rs_init(const double *__restrict__ pts, int64_t n, int axis,
+                          uint64_t *__restrict__ keys, int32_t *__restrict__ vals)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        keys[i] = order_key(pts[2 * i + axis]);
+        vals[i] = (int32_t)i;
+    }
+}
+
+__global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                                   int shift, int32_t *__restrict__ hist, int nblk)
+{
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_BLOCK;
+    for (int t = 0; t < RS_TILES; ++t) {
+        int64_t k = base + (int64_t)t * RS_T + threadIdx.x;
+        if (k < n) atomicAdd(&h[(keys[k] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict__ kin,
+                                                      const int32_t *__restrict__ vin,
+                                                      uint64_t *__restrict__ kout,
+                                                      int32_t *__restrict__ vout, int64_t n,
+                                                      int shift, const int32_t *__restrict__ off,
+                                                      int nblk)
+{
+    __shared__ int32_t run[256];
+    __shared__ int32_t wc[RS_T / WAVE][256];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    run[tid] = off[(int64_t)tid * nblk + blockIdx.x];
+    for (int q = 0; q < RS_T / WAVE; ++q) wc[q][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_BLOCK;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+    for (int t = 0; t < RS_TILES; ++t) {
+        int64_t k = base + (int64_t)t * RS_T + tid;
+        bool valid = k < n;
+        uint64_t key = valid ? kin[k] : 0ull;
+        int d = (int)((key >> shift) & 255);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (d >> b) & 1;
+            uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        int rank = __popcll(peers & lt);
+        bool leader = valid && rank == 0;
+        if (leader) wc[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int64_t pos = run[d] + rank;
+            for (int q = 0; q < w; ++q) pos += wc[q][d];
+            pos = pos < 0 ? 0 : (pos >= n ? n - 1 : pos); // never leave the array
+            kout[pos] = key;
+            vout[pos] = vin[k];
+        }
+        __syncthreads();
+        int32_t add = 0;
+        for (int q = 0; q < RS_T / WAVE; ++q) {
+            add += wc[q][tid];
+            wc[q][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// Sort indices 0..n-1 of pts by (coordinate `axis`, index) into out.
+static hipError_t presort(const double *pts, int64_t n, int axis, uint64_t *k0, uint64_t *k1,
+                          int32_t *v0, int32_t *v1, int32_t *hist, int32_t *bsum, int32_t *out,
+                          hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_rs_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pts, n, axis, k0, v0);
+    int nblk = (int)((n + RS_BLOCK - 1) / RS_BLOCK);
+    uint64_t *ka = k0, *kb = k1;
+    int32_t *va = v0, *vb = v1;
+    for (int pass = 0; pass < 8; ++pass) {
+        int shift = 8 * pass;
+        k_rs_hist<<<nblk, RS_T, 0, st>>>(ka, n, shift, hist, nblk);
+        hipError_t e = fmm_scan_i32(hist, hist, (int64_t)256 * nblk, nullptr, bsum, st);
+        if (e != hipSuccess) return e;
+        k_rs_scatter<<<nblk, RS_T, 0, st>>>(ka, va, kb, vb, n, shift, hist, nblk);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        int32_t *tv = va; va = vb; vb = tv;
+    }
+    return hipMemcpyAsync(out, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+}
+
+// ------------------------------------------------------------ splits --
+// Segment j of a step holds positions [start[j], start[j+1]).  Position ->
+// segment by binary search (empty segments are skipped: the largest j with
+// start[j] <= i).
+__device__ __forceinline__ int32_t seg_of(const int32_t *__restrict__ start, int32_t nseg, int64_t i)
+{
+    int32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)start[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct seg_args {
+    const double *src, *tgt;
+    const int32_t *slx, *sly;     // source lists sorted by x / y within segments
+    const int32_t *tlx, *tly;     // target lists (nt > 0)
+    const int32_t *sst, *tst;     // step starts (nseg+1)
+    int32_t *sst_next, *tst_next; // next step starts (2 nseg + 1), or NULL
+    uint8_t *axis;
+    int32_t *nlo, *tlo;
+    double *centre, *radius;      // level arrays (already offset), or NULL
+    int32_t *lvl_sst, *lvl_tst;   // per-level start output (already offset), or NULL
+    int32_t nseg;
+    int64_t ns, nt;
+};
+
+// One thread per segment: tight rectangle of its sources and targets, box
+// geometry (on even steps), split axis, median rank and target split count.
+__global__ void k_seg(seg_args a)
+{
+    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.nseg) return;
+    const int32_t s0 = a.sst[j], s1 = a.sst[j + 1];
+    const int32_t n = s1 - s0;
+    const int32_t t0 = a.nt ? a.tst[j] : 0, t1 = a.nt ? a.tst[j + 1] : 0;
+    const int32_t m = t1 - t0;
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    if (n > 0) {
+        x0 = a.src[2 * (int64_t)a.slx[s0]];
+        x1 = a.src[2 * (int64_t)a.slx[s1 - 1]];
+        y0 = a.src[2 * (int64_t)a.sly[s0] + 1];
+        y1 = a.src[2 * (int64_t)a.sly[s1 - 1] + 1];
+    }
+    if (m > 0) {
+        double u;
+        u = a.tgt[2 * (int64_t)a.tlx[t0]];          if (u < x0) x0 = u;
+        u = a.tgt[2 * (int64_t)a.tlx[t1 - 1]];      if (u > x1) x1 = u;
+        u = a.tgt[2 * (int64_t)a.tly[t0] + 1];      if (u < y0) y0 = u;
+        u = a.tgt[2 * (int64_t)a.tly[t1 - 1] + 1];  if (u > y1) y1 = u;
+    }
+    const double w = x1 - x0, h = y1 - y0;
+    if (a.centre) {
+        a.centre[2 * (int64_t)j] = 0.5 * (x0 + x1);
+        a.centre[2 * (int64_t)j + 1] = 0.5 * (y0 + y1);
+        a.radius[j] = 0.5 * sqrt(w * w + h * h);
+    }
+    if (a.lvl_sst) {
+        a.lvl_sst[j] = s0;
+        if (j == a.nseg - 1) a.lvl_sst[a.nseg] = s1;
+        if (a.nt) {
+            a.lvl_tst[j] = t0;
+            if (j == a.nseg - 1) a.lvl_tst[a.nseg] = t1;
+        }
+    }
+    if (!a.sst_next) return;
+    const int ax = (w >= h) ? 0 : 1;
+    const int32_t nl = n / 2;
+    int32_t tl = 0;
+    if (n > 0 && m > 0) {
+        const int32_t *A = ax ? a.sly : a.slx;
+        const double sv = a.src[2 * (int64_t)A[s0 + nl] + ax];
+        const int32_t *TA = ax ? a.tly : a.tlx;
+        int32_t lo = t0, hi = t1; // first position with coordinate >= sv
+        while (lo < hi) {
+            int32_t mid = lo + ((hi - lo) >> 1);
+            if (a.tgt[2 * (int64_t)TA[mid] + ax] >= sv) hi = mid; else lo = mid + 1;
+        }
+        tl = lo - t0;
+    }
+    a.axis[j] = (uint8_t)ax;
+    a.nlo[j] = nl;
+    a.tlo[j] = tl;
+    a.sst_next[2 * j] = s0;
+    a.sst_next[2 * j + 1] = s0 + nl;
+    if (j == a.nseg - 1) a.sst_next[2 * a.nseg] = s1;
+    if (a.nt) {
+        a.tst_next[2 * j] = t0;
+        a.tst_next[2 * j + 1] = t0 + tl;
+        if (j == a.nseg - 1) a.tst_next[2 * a.nseg] = t1;
+    }
+}
+
+// Side flag (0 = lo, 1 = hi) of every original index, from the axis list of
+// its segment: the first nlo positions are lo.
+__global__ void k_mark(const int32_t *__restrict__ lx, const int32_t *__restrict__ ly,
+                       const int32_t *__restrict__ start, int32_t nseg,
+                       const uint8_t *__restrict__ axis, const int32_t *__restrict__ nlo,
+                       int64_t n, uint8_t *__restrict__ side)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t j = seg_of(start, nseg, i);
+    const int32_t *A = axis[j] ? ly : lx;
+    side[A[i]] = (i - start[j] < nlo[j]) ? 0 : 1;
+}
+
+struct part_list {
+    const int32_t *in;
+    int32_t *out;
+    int32_t *bsum;        // nblk + 1
+    const uint8_t *side;
+    const int32_t *start; // segment starts (nseg + 1)
+    const int32_t *nlo;   // lo count per segment
+    const int32_t *LO;    // exclusive scan of nlo
+    int64_t n;
+    int32_t nseg;
+};
+struct part_batch {
+    part_list l[6];
+};
+
+__global__ void __launch_bounds__(SCAN_T) k_part_reduce(part_batch pb)
+{
+    const part_list &p = pb.l[blockIdx.y];
+    __shared__ int32_t sh[SCAN_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
+    if ((int64_t)blockIdx.x * SCAN_B >= p.n) return; // whole block idle (uniform)
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_I; ++i)
+        if (base + i < p.n) s += p.side[p.in[base + i]] == 0;
+    int32_t tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) p.bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_part_sums(part_batch pb)
+{
+    const part_list &p = pb.l[blockIdx.x];
+    __shared__ int32_t sh[1024 / WAVE];
+    const int64_t nb = fmm_scan_blocks(p.n);
+    int32_t carry = 0;
+    for (int64_t c = 0; c < nb; c += blockDim.x) {
+        int64_t k = c + threadIdx.x;
+        int32_t v = k < nb ? p.bsum[k] : 0;
+        int32_t tot;
+        int32_t ex = block_excl_scan(v, sh, &tot);
+        if (k < nb) p.bsum[k] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_part_scatter(part_batch pb)
+{
+    const part_list &p = pb.l[blockIdx.y];
+    __shared__ int32_t sh[SCAN_T / WAVE];
+    if ((int64_t)blockIdx.x * SCAN_B >= p.n) return;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
+    int32_t v[SCAN_I];
+    uint8_t lo[SCAN_I];
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_I; ++i) {
+        v[i] = (base + i < p.n) ? p.in[base + i] : 0;
+        lo[i] = (base + i < p.n) ? (p.side[v[i]] == 0) : 0;
+        s += lo[i];
+    }
+    int32_t tot;
+    int32_t run = block_excl_scan(s, sh, &tot) + p.bsum[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SCAN_I; ++i) {
+        int64_t pos = base + i;
+        if (pos < p.n) {
+            int32_t j = seg_of(p.start, p.nseg, pos);
+            int32_t st = p.start[j];
+            int32_t rank = run - p.LO[j]; // lo elements before pos in segment j
+            int64_t dst = lo[i] ? (int64_t)st + rank
+                                : (int64_t)st + p.nlo[j] + (pos - st - rank);
+            dst = dst < 0 ? 0 : (dst >= p.n ? p.n - 1 : dst); // never leave the array
+            p.out[dst] = v[i];
+        }
+        run += lo[i];
+    }
+}
+
+// ------------------------------------------------------------- lists --
+__device__ __forceinline__ bool theta_weak(double cbx, double cby, double rb, double csx,
+                                           double csy, double rs, double theta)
+{
+    const double dx = cbx - csx;
+    const double dy = cby - csy;
+    const double d = sqrt(dx * dx + dy * dy);
+    const double R = rb >= rs ? rb : rs;
+    const double r = rb >= rs ? rs : rb;
+    return d > 0.0 && R + theta * r <= theta * d;
+}
+
+struct list_args {
+    const double *centre, *radius; // level l arrays (offset)
+    const int32_t *psoff;          // level l-1 strong offsets (offset)
+    const int32_t *sidx;           // global strong list array
+    int32_t *wcnt, *scnt;          // counts (count pass)
+    const int32_t *woff, *soff;    // level l offsets (fill pass, offset)
+    int32_t *widx_out, *sidx_out;  // global arrays (fill pass)
+    int32_t nbl;
+    int32_t cap;
+    double theta;
+    int32_t *status;
+};
+
+template <bool FILL>
+__global__ void k_lists(list_args a)
+{
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nbl) return;
+    const int32_t q = b >> 2;
+    const int32_t e0 = min(a.psoff[q], a.cap), e1 = min(a.psoff[q + 1], a.cap);
+    const double cbx = a.centre[2 * (int64_t)b], cby = a.centre[2 * (int64_t)b + 1];
+    const double rb = a.radius[b];
+    int32_t nw = 0, nsg = 0;
+    int32_t wo = 0, so = 0, we = 0, se = 0;
+    if (FILL) {
+        wo = a.woff[b]; we = a.woff[b + 1];
+        so = a.soff[b]; se = a.soff[b + 1];
+        if (we > a.cap || se > a.cap) atomicOr(a.status, FMM_ST_LIST_OVERFLOW);
+    }
+    for (int32_t e = e0; e < e1; ++e) {
+        int32_t s = a.sidx[e];
+        s = min(max(s, 0), (a.nbl >> 2) - 1);
+        for (int k = 0; k < 4; ++k) {
+            const int32_t c = 4 * s + k;
+            const bool weak = (c != b) && theta_weak(cbx, cby, rb, a.centre[2 * (int64_t)c],
+                                                     a.centre[2 * (int64_t)c + 1], a.radius[c],
+                                                     a.theta);
+            if (weak) {
+                if (FILL && wo + nw < a.cap) a.widx_out[wo + nw] = c;
+                ++nw;
+            } else {
+                if (FILL && so + nsg < a.cap) a.sidx_out[so + nsg] = c;
+                ++nsg;
+            }
+        }
+    }
+    if (!FILL) {
+        a.wcnt[b] = nw;
+        a.scnt[b] = nsg;
+    }
+}
+
+__global__ void k_root(int32_t *sstep, int32_t ns, int32_t *tstep, int32_t nt)
+{
+    sstep[0] = 0; sstep[1] = ns;
+    tstep[0] = 0; tstep[1] = nt;
+}
+
+__global__ void k_lists_root(int32_t *woff, int32_t *soff, int32_t *sidx)
+{
+    woff[0] = 0; woff[1] = 0;
+    soff[0] = 0; soff[1] = 1;
+    sidx[0] = 0;
+}
+
+__global__ void k_gather(const double *__restrict__ src, const double *__restrict__ m,
+                         const int32_t *__restrict__ perm, int64_t ns, double4 *__restrict__ srcs,
+                         float2 *__restrict__ m32, const double *__restrict__ tgt,
+                         const int32_t *__restrict__ tperm, int64_t nt, double2 *__restrict__ tgts)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ns) {
+        int64_t j = perm[i];
+        srcs[i] = make_double4(src[2 * j], src[2 * j + 1], m[2 * j], m[2 * j + 1]);
+        if (m32) m32[i] = make_float2((float)m[2 * j], (float)m[2 * j + 1]);
+    }
+    if (i < nt) {
+        int64_t j = tperm[i];
+        tgts[i] = make_double2(tgt[2 * j], tgt[2 * j + 1]);
+    }
+}
+
+#define WS(T, off) reinterpret_cast<T *>(a.ws + (off))
+#define CK(x) do { hipError_t e__ = (x); if (e__ != hipSuccess) return e__; } while (0)
+
+static inline unsigned nblk256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t st)
+{
+    const fmm_layout &lay = *a.lay;
+    const int L = a.L;
+    const int64_t ns = a.ns, nt = a.nt;
+    uint64_t *k0 = WS(uint64_t, lay.keys[0]), *k1 = WS(uint64_t, lay.keys[1]);
+    int32_t *v0 = WS(int32_t, lay.vals[0]), *v1 = WS(int32_t, lay.vals[1]);
+    int32_t *hist = WS(int32_t, lay.hist);
+    int32_t *bsum = WS(int32_t, lay.bsum);
+    // list buffers: [0..2] current lx, ly, li; [3..5] partition outputs
+    int32_t *sl[6], *tl[6];
+    for (int i = 0; i < 6; ++i) {
+        sl[i] = WS(int32_t, lay.sl[0]) + (int64_t)i * ns;
+        tl[i] = nt ? WS(int32_t, lay.tl[0]) + (int64_t)i * nt : nullptr;
+    }
+    uint8_t *sside = WS(uint8_t, lay.sside), *tside = nt ? WS(uint8_t, lay.tside) : nullptr;
+    int32_t *sstep = WS(int32_t, lay.sstep), *tstep = WS(int32_t, lay.tstep);
+    uint8_t *axis = WS(uint8_t, lay.seg_axis);
+    int32_t *nlo = WS(int32_t, lay.seg_nlo), *tlo = WS(int32_t, lay.seg_tlo);
+    int32_t *LO = WS(int32_t, lay.seg_LO), *TLO = WS(int32_t, lay.seg_TLO);
+    int32_t *sstart = WS(int32_t, lay.sstart), *tstart = WS(int32_t, lay.tstart);
+    double *centre = WS(double, lay.centre), *radius = WS(double, lay.radius);
+
+    // presort: x- and y-ordered lists; index-ordered list
+    CK(presort(a.src, ns, 0, k0, k1, v0, v1, hist, bsum, sl[0], st));
+    CK(presort(a.src, ns, 1, k0, k1, v0, v1, hist, bsum, sl[1], st));
+    if (nt) {
+        CK(presort(a.tgt, nt, 0, k0, k1, v0, v1, hist, bsum, tl[0], st));
+        CK(presort(a.tgt, nt, 1, k0, k1, v0, v1, hist, bsum, tl[1], st));
+    }
+    // identity lists and the root segment
+    {
+        int64_t nmax = ns > nt ? ns : nt;
+        // k_rs_init writes vals = identity; reuse it through a tiny lambda-free kernel
+        k_rs_init<<<nblk256(ns), 256, 0, st>>>(a.src, ns, 0, k0, sl[2]);
+        if (nt) k_rs_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, nt, 0, k0, tl[2]);
+        (void)nmax;
+        k_root<<<1, 1, 0, st>>>(sstep, (int32_t)ns, tstep, (int32_t)nt);
+    }
+    int64_t soff_k = 0; // offset of step k's starts
+    for (int k = 0; k <= 2 * L; ++k) {
+        const int32_t nseg = (int32_t)(((int64_t)1) << k);
+        const bool split = k < 2 * L;
+        const bool even = (k % 2) == 0;
+        const int l = k / 2;
+        seg_args sa;
+        sa.src = a.src; sa.tgt = a.tgt;
+        sa.slx = sl[0]; sa.sly = sl[1];
+        sa.tlx = tl[0]; sa.tly = tl[1];
+        sa.sst = sstep + soff_k; sa.tst = tstep + soff_k;
+        sa.sst_next = split ? sstep + soff_k + nseg + 1 : nullptr;
+        sa.tst_next = split ? tstep + soff_k + nseg + 1 : nullptr;
+        sa.axis = axis; sa.nlo = nlo; sa.tlo = tlo;
+        sa.centre = even ? centre + 2 * box_off(l) : nullptr;
+        sa.radius = even ? radius + box_off(l) : nullptr;
+        sa.lvl_sst = even ? sstart + start_off(l) : nullptr;
+        sa.lvl_tst = even ? tstart + start_off(l) : nullptr;
+        sa.nseg = nseg; sa.ns = ns; sa.nt = nt;
+        k_seg<<<nblk256(nseg), 256, 0, st>>>(sa);
+        CK(hipGetLastError());
+        if (!split) break;
+        // exclusive scans of the lo counts over segments
+        CK(fmm_scan_i32(nlo, LO, nseg, nullptr, hist, st));
+        if (nt) CK(fmm_scan_i32(tlo, TLO, nseg, nullptr, hist, st));
+        k_mark<<<nblk256(ns), 256, 0, st>>>(sl[0], sl[1], sstep + soff_k, nseg, axis, nlo, ns, sside);
+        if (nt)
+            k_mark<<<nblk256(nt), 256, 0, st>>>(tl[0], tl[1], tstep + soff_k, nseg, axis, tlo, nt, tside);
+        part_batch pb;
+        int nl = 0;
+        int64_t bsum_stride = fmm_scan_blocks(ns > nt ? ns : nt) + 1;
+        for (int q = 0; q < 3; ++q) {
+            part_list &p = pb.l[nl];
+            p.in = sl[q]; p.out = sl[3 + q];
+            p.bsum = bsum + (int64_t)nl * bsum_stride;
+            p.side = sside; p.start = sstep + soff_k; p.nlo = nlo; p.LO = LO;
+            p.n = ns; p.nseg = nseg;
+            ++nl;
+        }
+        if (nt) {
+            for (int q = 0; q < 3; ++q) {
+                part_list &p = pb.l[nl];
+                p.in = tl[q]; p.out = tl[3 + q];
+                p.bsum = bsum + (int64_t)nl * bsum_stride;
+                p.side = tside; p.start = tstep + soff_k; p.nlo = tlo; p.LO = TLO;
+                p.n = nt; p.nseg = nseg;
+                ++nl;
+            }
+        }
+        const int64_t nmax = ns > nt ? ns : nt;
+        dim3 g((unsigned)fmm_scan_blocks(nmax), (unsigned)nl);
+        k_part_reduce<<<g, SCAN_T, 0, st>>>(pb);
+        k_part_sums<<<nl, 1024, 0, st>>>(pb);
+        k_part_scatter<<<g, SCAN_T, 0, st>>>(pb);
+        CK(hipGetLastError());
+        for (int q = 0; q < 3; ++q) {
+            int32_t *t = sl[q]; sl[q] = sl[3 + q]; sl[3 + q] = t;
+            if (nt) { t = tl[q]; tl[q] = tl[3 + q]; tl[3 + q] = t; }
+        }
+        soff_k += nseg + 1;
+    }
+    // perm / tperm: the index-ordered lists, gathered points
+    int32_t *perm = sl[2];
+    int32_t *tperm = nt ? tl[2] : nullptr;
+    if (perm != WS(int32_t, lay.sl[0]) + 2 * ns) {
+        CK(hipMemcpyAsync(WS(int32_t, lay.sl[0]) + 2 * ns, perm, (size_t)ns * 4,
+                          hipMemcpyDeviceToDevice, st));
+    }
+    if (nt && tperm != WS(int32_t, lay.tl[0]) + 2 * nt) {
+        CK(hipMemcpyAsync(WS(int32_t, lay.tl[0]) + 2 * nt, tperm, (size_t)nt * 4,
+                          hipMemcpyDeviceToDevice, st));
+    }
+    perm = WS(int32_t, lay.sl[0]) + 2 * ns;
+    tperm = nt ? WS(int32_t, lay.tl[0]) + 2 * nt : nullptr;
+    {
+        int64_t nmax = ns > nt ? ns : nt;
+        k_gather<<<nblk256(nmax), 256, 0, st>>>(a.src, m, perm, ns, WS(double4, lay.srcs),
+                                                lay.mixed ? WS(float2, lay.m32) : nullptr, a.tgt,
+                                                tperm, nt, nt ? WS(double2, lay.tgts) : nullptr);
+        CK(hipGetLastError());
+    }
+
+    return hipSuccess;
+}
+
+// Interaction lists, level by level (count, scan, fill).
+hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st)
+{
+    const fmm_layout &lay = *a.lay;
+    const int L = a.L;
+    double *centre = WS(double, lay.centre), *radius = WS(double, lay.radius);
+    int32_t *woff = WS(int32_t, lay.woff), *soff = WS(int32_t, lay.soff);
+    int32_t *widx = WS(int32_t, lay.widx), *sidx = WS(int32_t, lay.sidx);
+    int32_t *wcnt = WS(int32_t, lay.wcnt), *scnt = WS(int32_t, lay.scnt);
+    int32_t *lbsum = WS(int32_t, lay.lbsum);
+    k_lists_root<<<1, 1, 0, st>>>(woff, soff, sidx);
+    for (int l = 1; l <= L; ++l) {
+        list_args la;
+        la.centre = centre + 2 * box_off(l);
+        la.radius = radius + box_off(l);
+        la.psoff = soff + start_off(l - 1);
+        la.sidx = sidx;
+        la.wcnt = wcnt; la.scnt = scnt;
+        la.woff = woff + start_off(l);
+        la.soff = soff + start_off(l);
+        la.widx_out = widx; la.sidx_out = sidx;
+        la.nbl = (int32_t)nbox(l);
+        la.cap = (int32_t)lay.listcap;
+        la.theta = a.theta;
+        la.status = a.status;
+        k_lists<false><<<nblk256(nbox(l)), 256, 0, st>>>(la);
+        CK(fmm_scan_i32(wcnt, woff + start_off(l), nbox(l), woff + start_off(l - 1) + nbox(l - 1),
+                        lbsum, st));
+        CK(fmm_scan_i32(scnt, soff + start_off(l), nbox(l), soff + start_off(l - 1) + nbox(l - 1),
+                        lbsum, st));
+        k_lists<true><<<nblk256(nbox(l)), 256, 0, st>>>(la);
+        CK(hipGetLastError());
+    }
+    return hipSuccess;
+}

@@ -1,0 +1,309 @@
+"""Thin Python binding of libfmm2d.so (the C ABI in include/fmm2d.h).
+
+Argument marshalling only: every step of the evaluation runs in the library's
+HIP kernels.  PyTorch provides device memory (inputs, outputs, workspace) and
+the current HIP stream.  Loading fails loudly when the library has not been
+built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm2d.so")
+
+OK, EINVAL, ENOSPC, EHIP, ENOMODEL = 0, -1, -2, -3, -4
+KERNEL = {"log": 1, "harmonic": 2}
+PRECISION = {"fp64": 0, "mixed": 1}
+PORDER = {"fixed": 0, "learned": 1}
+FLAG_TIMING = 1
+FLAG_REQUIRE_MODEL = 2
+PHASES = ("tree", "lists", "p2m", "m2m", "porder", "m2l", "l2l", "p2p")
+
+#: every symbol include/fmm2d.h declares
+EXPORTS = ("fmm2d_default_opts", "fmm2d_create", "fmm2d_destroy", "fmm2d_last_error",
+           "fmm2d_nlevels", "fmm2d_workspace_size", "fmm2d_eval", "fmm2d_direct",
+           "fmm2d_sync", "fmm2d_get_topology", "fmm2d_get_stats")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("tol", ctypes.c_double), ("p", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("leaf_target", ctypes.c_int32),
+                ("kernel", ctypes.c_uint32), ("precision", ctypes.c_uint32),
+                ("porder", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("list_cap", ctypes.c_int32)]
+
+
+class Topology(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("p", ctypes.c_int32), ("n_src", ctypes.c_int64),
+                ("n_tgt", ctypes.c_int64)] + [
+        (n, ctypes.c_void_p) for n in ("perm", "tperm", "sstart", "tstart", "centre", "radius",
+                                       "weak_off", "weak_idx", "strong_off", "strong_idx",
+                                       "mpole", "local", "porder")]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_float * 8), ("n_weak", ctypes.c_int64),
+                ("n_strong", ctypes.c_int64), ("n_p2p_pairs", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("used_model", ctypes.c_int32),
+                ("p_hist", ctypes.c_int64 * 65)]
+
+
+_lib = None
+
+
+def load():
+    """Load libfmm2d.so; raises if it is missing (build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfmm2d.so not built: run `python -m paper_1205_4611_amd.build` "
+                           "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+    lib.fmm2d_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.fmm2d_default_opts.restype = None
+    lib.fmm2d_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    lib.fmm2d_create.restype = ctypes.c_int
+    lib.fmm2d_destroy.argtypes = [P]
+    lib.fmm2d_destroy.restype = None
+    lib.fmm2d_last_error.argtypes = [P]
+    lib.fmm2d_last_error.restype = ctypes.c_char_p
+    lib.fmm2d_nlevels.argtypes = [i64, i32]
+    lib.fmm2d_nlevels.restype = ctypes.c_int
+    lib.fmm2d_workspace_size.argtypes = [P, i64, i64, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_size_t)]
+    lib.fmm2d_workspace_size.restype = ctypes.c_int
+    lib.fmm2d_eval.argtypes = [P, i64, P, P, i64, P, ctypes.POINTER(Opts), P, P, P, ctypes.c_size_t, P]
+    lib.fmm2d_eval.restype = ctypes.c_int
+    lib.fmm2d_direct.argtypes = [P, i64, P, P, i64, P, P, i64, u32, P, P, P]
+    lib.fmm2d_direct.restype = ctypes.c_int
+    lib.fmm2d_sync.argtypes = [P, P]
+    lib.fmm2d_sync.restype = ctypes.c_int
+    lib.fmm2d_get_topology.argtypes = [P, ctypes.POINTER(Topology)]
+    lib.fmm2d_get_topology.restype = ctypes.c_int
+    lib.fmm2d_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.fmm2d_get_stats.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class FMMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("fmm2d error %d: %s" % (code, msg))
+        self.code = code
+
+
+def nlevels(n: int, nd: int) -> int:
+    return int(load().fmm2d_nlevels(int(n), int(nd)))
+
+
+def make_opts(theta=0.5, tol=1e-6, p=0, levels=-1, leaf_target=45, kernel="log",
+              precision="fp64", porder="fixed", timing=False, require_model=False,
+              list_cap=0) -> Opts:
+    o = Opts()
+    load().fmm2d_default_opts(ctypes.byref(o))
+    o.theta = float(theta)
+    o.tol = float(tol)
+    o.p = int(p)
+    o.levels = int(levels)
+    o.leaf_target = int(leaf_target)
+    o.kernel = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
+    o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.porder = PORDER[porder] if isinstance(porder, str) else int(porder)
+    o.flags = (FLAG_TIMING if timing else 0) | (FLAG_REQUIRE_MODEL if require_model else 0)
+    o.list_cap = int(list_cap)
+    return o
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _as_points(z, name):
+    """complex128 [n] or float64 [n,2] CUDA tensor -> contiguous float64 [n,2]."""
+    if z is None:
+        return None
+    if not isinstance(z, torch.Tensor) or not z.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if z.is_complex():
+        z = torch.view_as_real(z.to(torch.complex128).contiguous())
+    if z.dtype != torch.float64 or z.dim() != 2 or z.shape[1] != 2:
+        raise TypeError("%s must be complex128 [n] or float64 [n,2]" % name)
+    return z.contiguous()
+
+
+class FMM2D:
+    """One library handle on one device, with a reusable workspace tensor."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        rc = self.lib.fmm2d_create(ctypes.byref(h), self.device)
+        if rc != OK:
+            raise FMMError(rc, "fmm2d_create failed")
+        self.h = h
+        self.ws = None
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fmm2d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc):
+        msg = self.lib.fmm2d_last_error(self.h)
+        return FMMError(rc, msg.decode() if msg else "")
+
+    def workspace_size(self, n_src, n_tgt=0, opts=None, **kw) -> int:
+        o = opts if opts is not None else make_opts(**kw)
+        b = ctypes.c_size_t()
+        rc = self.lib.fmm2d_workspace_size(self.h, int(n_src), int(n_tgt), ctypes.byref(o), ctypes.byref(b))
+        if rc != OK:
+            raise self._err(rc)
+        return int(b.value)
+
+    def _workspace(self, nbytes):
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:%d" % self.device)
+        return self.ws
+
+    def eval(self, src, m, tgt=None, *, opts=None, phi=None, dphi=None, check=True, **kw):
+        """Evaluate Phi, Phi' (complex128 CUDA tensors in the caller's target
+        order).  Returns (phi, dphi); phi is None for the harmonic kernel.
+        check=True synchronises and raises on device-side errors."""
+        o = opts if opts is not None else make_opts(**kw)
+        s = _as_points(src, "src")
+        mm = _as_points(m, "m")
+        t = _as_points(tgt, "tgt")
+        ns = s.shape[0]
+        nt = ns if t is None else t.shape[0]
+        dev = s.device
+        log = o.kernel == KERNEL["log"]
+        if dphi is None:
+            dphi = torch.empty(nt, dtype=torch.complex128, device=dev)
+        if log and phi is None:
+            phi = torch.empty(nt, dtype=torch.complex128, device=dev)
+        nbytes = self.workspace_size(ns, 0 if t is None else nt, o)
+        ws = self._workspace(nbytes)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self._keep = (s, mm, t)
+        rc = self.lib.fmm2d_eval(self.h, ns, _ptr(s), _ptr(mm), nt if t is not None else 0, _ptr(t),
+                                 ctypes.byref(o), _ptr(phi) if log else None, _ptr(dphi), _ptr(ws),
+                                 ws.numel(), ctypes.c_void_p(stream))
+        if rc != OK:
+            raise self._err(rc)
+        if check:
+            self.sync()
+        return (phi if log else None), dphi
+
+    def sync(self):
+        stream = torch.cuda.current_stream(torch.device("cuda", self.device)).cuda_stream
+        rc = self.lib.fmm2d_sync(self.h, ctypes.c_void_p(stream))
+        if rc != OK:
+            raise self._err(rc)
+
+    def direct(self, src, m, tgt=None, tsel=None, kernel="log"):
+        """Device direct sum of Phi, Phi' over all sources (optionally at the
+        targets tsel, an int64 CUDA tensor).  Returns (phi, dphi)."""
+        s = _as_points(src, "src")
+        mm = _as_points(m, "m")
+        t = _as_points(tgt, "tgt")
+        ns = s.shape[0]
+        nt = ns if t is None else t.shape[0]
+        k = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
+        if tsel is not None:
+            tsel = tsel.to(device=s.device, dtype=torch.int64).contiguous()
+        nout = nt if tsel is None else tsel.numel()
+        dphi = torch.empty(nout, dtype=torch.complex128, device=s.device)
+        phi = torch.empty(nout, dtype=torch.complex128, device=s.device) if k == 1 else None
+        stream = torch.cuda.current_stream(s.device).cuda_stream
+        rc = self.lib.fmm2d_direct(self.h, ns, _ptr(s), _ptr(mm), nt, _ptr(t), _ptr(tsel),
+                                   0 if tsel is None else tsel.numel(), k, _ptr(phi), _ptr(dphi),
+                                   ctypes.c_void_p(stream))
+        if rc != OK:
+            raise self._err(rc)
+        return phi, dphi
+
+    def stats(self) -> dict:
+        st = Stats()
+        rc = self.lib.fmm2d_get_stats(self.h, ctypes.byref(st))
+        if rc != OK:
+            raise self._err(rc)
+        return {"ms": {k: float(st.ms[i]) for i, k in enumerate(PHASES)}, "n_weak": st.n_weak,
+                "n_strong": st.n_strong, "n_p2p_pairs": st.n_p2p_pairs, "status": st.status,
+                "used_model": st.used_model, "p_hist": list(st.p_hist)}
+
+    def topology(self, coeffs: bool = False) -> dict:
+        """Host (numpy) copies of the tree, lists (and coefficients) of the
+        last evaluation, for the tests."""
+        import numpy as np
+        tp = Topology()
+        rc = self.lib.fmm2d_get_topology(self.h, ctypes.byref(tp))
+        if rc != OK:
+            raise self._err(rc)
+        self.sync()
+        L, p = tp.levels, tp.p
+        nb = (4 ** (L + 1) - 1) // 3
+        nst = nb + L + 1
+
+        def dev(ptr, n, dtype):
+            n = int(n)
+            if n == 0:
+                return np.empty(0, dtype=dtype)
+            tmp = torch.empty(n * np.dtype(dtype).itemsize, dtype=torch.uint8)
+            _memcpy_d2h(tmp, ptr, tmp.numel())
+            return tmp.numpy().view(dtype).copy()
+
+        woff = dev(tp.weak_off, nst, np.int32)
+        soff = dev(tp.strong_off, nst, np.int32)
+        so_L = nb - 4 ** L + L  # start offset of level L
+        nw = int(woff[so_L + 4 ** L])
+        nsg = int(soff[so_L + 4 ** L])
+        out = {
+            "levels": L, "p": p,
+            "perm": dev(tp.perm, tp.n_src, np.int32),
+            "tperm": dev(tp.tperm, tp.n_tgt, np.int32),
+            "sstart": dev(tp.sstart, nst, np.int32),
+            "tstart": dev(tp.tstart, nst, np.int32),
+            "centre": dev(tp.centre, 2 * nb, np.float64).view(np.complex128),
+            "radius": dev(tp.radius, nb, np.float64),
+            "weak_off": woff, "weak_idx": dev(tp.weak_idx, nw, np.int32),
+            "strong_off": soff, "strong_idx": dev(tp.strong_idx, nsg, np.int32),
+        }
+        if coeffs:
+            out["mpole"] = dev(tp.mpole, 2 * nb * (p + 1), np.float64).view(np.complex128).reshape(nb, p + 1)
+            out["local"] = dev(tp.local, 2 * nb * (p + 1), np.float64).view(np.complex128).reshape(nb, p + 1)
+        return out
+
+
+def _memcpy_d2h(host_u8: torch.Tensor, dev_ptr: int, nbytes: int):
+    """Copy nbytes from a raw device address into a host uint8 tensor."""
+    lib = _hip()
+    rc = lib.hipMemcpy(ctypes.c_void_p(host_u8.data_ptr()), ctypes.c_void_p(dev_ptr),
+                       ctypes.c_size_t(nbytes), 2)  # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise RuntimeError("hipMemcpy failed (%d)" % rc)
+
+
+_hiplib = None
+
+
+def _hip():
+    global _hiplib
+    if _hiplib is None:
+        _hiplib = ctypes.CDLL("libamdhip64.so")
+        _hiplib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hiplib.hipMemcpy.restype = ctypes.c_int
+    return _hiplib

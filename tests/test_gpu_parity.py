@@ -1,0 +1,218 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tree, permutation, geometry and lists: bit-exact.  Potentials: FP64 GPU FMM
+against the oracle FMM at equal p and lists (<= 1e-12 normwise: only the
+summation order differs), against the direct sum within the pointwise TOL of
+Sec. 5.1, and the direct-sum kernel against the oracle's compensated sum.
+"""
+import numpy as np
+import pytest
+
+from paper_1205_4611_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(z):
+    return None if z is None else torch.from_numpy(np.ascontiguousarray(z, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def nrm(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1205_4611_amd import fmm2d
+    f = fmm2d.FMM2D(0)
+    yield f
+    f.close()
+
+
+# ------------------------------------------------------------------ direct
+def test_direct_matches_oracle(fmm, orc):
+    src = workloads.points("uniform", 3000, 61)
+    m = workloads.strengths(3000, 62)
+    tgt = np.concatenate([workloads.points("uniform", 900, 63), src[:100]])
+    for tg in (None, tgt):
+        for kernel, kname in ((orc.KERNEL_LOG, "log"), (orc.KERNEL_HARMONIC, "harmonic")):
+            rp, rd = orc.direct(src, m, tgt=tg, kernel=kernel)
+            gp, gd = fmm.direct(dev(src), dev(m), dev(tg), kernel=kname)
+            torch.cuda.synchronize()
+            assert nrm(host(gd), rd) < 1e-13
+            if kernel == orc.KERNEL_LOG:
+                assert nrm(host(gp), rp) < 1e-13
+    sel = np.array([5, 17, 2999, 0, 1234], np.int64)
+    rp, rd = orc.direct(src, m, tsel=sel)
+    gp, gd = fmm.direct(dev(src), dev(m), tsel=torch.from_numpy(sel).cuda())
+    assert nrm(host(gd), rd) < 1e-13 and nrm(host(gp), rp) < 1e-13
+
+
+# ------------------------------------------------------------------ tree
+TREE_CASES = [
+    # name, dist, n, L, target spec (dist, n, seed) or None
+    ("uniform10k", "uniform", 10_000, 4, None),
+    ("clusters20k", "clusters", 20_000, 5, None),
+    ("spiral_ragged", "spiral", 10_007, 4, None),
+    ("gauss10_targets", "gauss10", 6_000, 3, ("gauss10", 4_000, 71)),
+    ("circle_targets", "circle", 5_000, 3, ("circle", 5_003, 72)),
+    ("normal_L0", "normal", 333, 0, None),
+    ("layer_L1_targets", "layer", 50, 1, ("uniform", 7, 73)),
+]
+
+
+def _lattice():
+    k = 24
+    return (np.arange(k)[:, None] + 1j * np.arange(k)[None, :]).ravel() / k
+
+
+def _case(name):
+    for c in TREE_CASES:
+        if c[0] == name:
+            _, dist, n, L, tspec = c
+            src = workloads.points(dist, n, 70)
+            tgt = None if tspec is None else workloads.points(tspec[0], tspec[1], tspec[2])
+            return src, tgt, L
+    if name == "lattice_ties":
+        g = _lattice()
+        return g, np.concatenate([g[::7], workloads.points("uniform", 40, 74)]), 2
+    raise KeyError(name)
+
+
+def _compare_topology(orc, top, T, L):
+    assert np.array_equal(top["perm"], T.perm)
+    nt = T.nt or T.ns
+    assert np.array_equal(top["tperm"][:nt], T.tperm[:nt])
+    assert np.array_equal(top["sstart"].astype(np.int64), T.sstart)
+    assert np.array_equal(top["tstart"].astype(np.int64), T.tstart)
+    # geometry bit for bit
+    assert np.array_equal(top["centre"].view(np.uint64), T.centre.view(np.uint64))
+    assert np.array_equal(top["radius"].view(np.uint64), T.radius.view(np.uint64))
+    for l in range(L + 1):
+        so = orc.start_offset(l)
+        nbl = 4 ** l
+        for key, lists in (("weak", T.weak), ("strong", T.strong)):
+            off = top[key + "_off"][so:so + nbl + 1].astype(np.int64)
+            idx = top[key + "_idx"][off[0]:off[-1]]
+            ro, ri = lists[l]
+            assert np.array_equal(off - off[0], ro), (key, l)
+            assert np.array_equal(idx, ri), (key, l)
+
+
+@pytest.mark.parametrize("name", [c[0] for c in TREE_CASES] + ["lattice_ties"])
+def test_tree_and_lists_bitexact(fmm, orc, name):
+    src, tgt, L = _case(name)
+    m = workloads.strengths(len(src), 75)
+    fmm.eval(dev(src), dev(m), dev(tgt), p=8, levels=L, kernel="harmonic")
+    top = fmm.topology()
+    T = orc.Tree(src, L, tgt=tgt)
+    _compare_topology(orc, top, T, L)
+
+
+# ------------------------------------------------------------------ FMM
+@pytest.mark.parametrize("kernel", ["log", "harmonic"])
+@pytest.mark.parametrize("name,p", [("uniform10k", 17), ("clusters20k", 12), ("gauss10_targets", 20),
+                                    ("lattice_ties", 30), ("spiral_ragged", 9)])
+def test_fmm_matches_oracle_fmm(fmm, orc, name, p, kernel):
+    src, tgt, L = _case(name)
+    m = workloads.strengths(len(src), 76)
+    k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
+    gp, gd = fmm.eval(dev(src), dev(m), dev(tgt), p=p, levels=L, kernel=kernel)
+    top = fmm.topology(coeffs=True)
+    T = orc.Tree(src, L, tgt=tgt)
+    rp, rd, A, B = T.eval(m, p, k, want_coeffs=True)
+    # coefficients weighted by their size on the box's disc: a_k / rho^k and
+    # b_l rho^l (raw high-order coefficients carry rounding relative to terms
+    # that cancel; the weighted ones measure what reaches the potential)
+    kk = np.arange(p + 1)
+    for l in range(L + 1):
+        s = T.boxes(l)
+        rho = np.maximum(T.radius[s], 1e-300)[:, None]
+        assert nrm(top["mpole"][s] / rho ** kk, A[s] / rho ** kk) < 1e-12, ("multipole", l)
+        if l >= 1:
+            assert nrm(top["local"][s] * rho ** kk, B[s] * rho ** kk) < 1e-12, ("local", l)
+    assert nrm(host(gd), rd) < 1e-12
+    if kernel == "log":
+        assert nrm(host(gp), rp) < 1e-12
+
+
+def test_l0_is_direct(fmm, orc):
+    src = workloads.points("clusters", 700, 77)
+    m = workloads.strengths(700, 78)
+    gp, gd = fmm.eval(dev(src), dev(m), p=5, levels=0, kernel="log")
+    rp, rd = orc.direct(src, m)
+    assert nrm(host(gd), rd) < 1e-13 and nrm(host(gp), rp) < 1e-13
+
+
+def test_operating_point_tol(fmm, orc):
+    """10,000 uniform sources at the sources, theta 1/2, p = 17: pointwise
+    relative error of Phi' about 1e-6 (TOL of Sec. 5.1), Phi against the
+    branch-consistent direct sum."""
+    src = workloads.points("uniform", 10_000, 1)
+    m = workloads.strengths(10_000, 101)
+    L = orc.nlevels(10_000, 40)
+    gp, gd = fmm.eval(dev(src), dev(m), p=17, levels=L, kernel="log")
+    _, rd = orc.direct(src, m, kernel=orc.KERNEL_HARMONIC)
+    err_pt = float(np.max(np.abs(host(gd) - rd) / np.abs(rd)))
+    assert err_pt < 2e-6, err_pt
+    T = orc.Tree(src, L)
+    sel = workloads.sample_indices(10_000, 500, 3)
+    rb = T.direct_branch(m, sel)
+    assert nrm(host(gp)[sel], rb) < 1e-8
+
+
+def test_deterministic(fmm):
+    src = workloads.points("clusters", 30_000, 79)
+    m = workloads.strengths(30_000, 80)
+    a = fmm.eval(dev(src), dev(m), p=17, kernel="log")
+    b = fmm.eval(dev(src), dev(m), p=17, kernel="log")
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------ errors
+def test_error_paths(fmm):
+    from paper_1205_4611_amd import fmm2d
+    src = dev(workloads.points("uniform", 100, 81))
+    m = dev(workloads.strengths(100, 82))
+    for kw in (dict(theta=1.5), dict(theta=0.0), dict(p=100), dict(levels=4), dict(p=0, tol=-1.0),
+               dict(leaf_target=0)):
+        with pytest.raises(fmm2d.FMMError) as e:
+            fmm.eval(src, m, **kw)
+        assert e.value.code == fmm2d.EINVAL, kw
+    # list overflow is found on the device and reported by the sync
+    with pytest.raises(fmm2d.FMMError) as e:
+        fmm.eval(dev(workloads.points("uniform", 5000, 83)), dev(workloads.strengths(5000, 84)),
+                 levels=4, list_cap=1)
+    assert e.value.code == fmm2d.ENOSPC
+    # the handle still works afterwards
+    fmm.eval(src, m, levels=1, p=4)
+
+
+# ------------------------------------------------------------------ mixed
+@pytest.mark.parametrize("kernel", ["log", "harmonic"])
+@pytest.mark.parametrize("name", ["clusters20k", "gauss10_targets"])
+def test_mixed_close_to_fp64(fmm, orc, name, kernel):
+    """FP32 P2P and FP32 M2L (radius-scaled, MFMA) against the FP64 oracle FMM
+    at the same order and lists: the FP32 rounding stays near 1e-7 relative
+    to the potential's scale (normwise)."""
+    src, tgt, L = _case(name)
+    m = workloads.strengths(len(src), 85)
+    k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
+    gp, gd = fmm.eval(dev(src), dev(m), dev(tgt), p=17, levels=L, kernel=kernel, precision="mixed")
+    T = orc.Tree(src, L, tgt=tgt)
+    rp, rd = T.eval(m, 17, k)
+    e_d = nrm(host(gd), rd)
+    print("mixed %s %s: dphi normwise %.2e" % (name, kernel, e_d))
+    assert e_d < 2e-6
+    if kernel == "log":
+        e_p = nrm(host(gp), rp)
+        print("mixed %s %s: phi normwise %.2e" % (name, kernel, e_p))
+        assert e_p < 2e-6
