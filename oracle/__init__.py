@@ -75,11 +75,12 @@ def _configure(lib):
     lib.orc_m2m.argtypes = [i32, P, f64, f64, P]
     lib.orc_m2l.argtypes = [i32, P, f64, f64, P]
     lib.orc_l2l.argtypes = [i32, P, f64, f64, P]
+    lib.orc_p2l.argtypes = [i32, i32, f64, f64, i64, P, P, P]
     lib.orc_eval_multipole.argtypes = [i32, P, f64, f64, f64, f64, P, P]
     lib.orc_eval_local.argtypes = [i32, P, f64, f64, f64, f64, P, P]
-    for f in ("orc_p2m", "orc_m2m", "orc_m2l", "orc_l2l", "orc_eval_multipole", "orc_eval_local"):
+    for f in ("orc_p2m", "orc_m2m", "orc_m2l", "orc_l2l", "orc_p2l", "orc_eval_multipole", "orc_eval_local"):
         getattr(lib, f).restype = None
-    lib.orc_build.argtypes = [i64, P, i64, P, i32, f64]
+    lib.orc_build.argtypes = [i64, P, i64, P, i32, f64, i32]
     lib.orc_build.restype = P
     lib.orc_free.argtypes = [P]
     lib.orc_free.restype = None
@@ -197,6 +198,16 @@ def m2l(p, a_src, rho, out=None):
     return o.view(np.complex128)
 
 
+def p2l(kernel, p, c, x, m, out=None):
+    """Local coefficients b_0..b_p about c of sources x (complex) lying outside
+    the expansion disc (leaf-level swapped criterion, Sec. 2)."""
+    x = _c(x, np.float64)
+    mm = _c(m, np.float64)
+    o = np.zeros(2 * (p + 1)) if out is None else _c(out, np.float64).copy()
+    _load().orc_p2l(kernel, p, float(np.real(c)), float(np.imag(c)), x.size // 2, _p(x), _p(mm), _p(o))
+    return o.view(np.complex128)
+
+
 def l2l(p, b_par, r, out=None):
     """Re-centre a local expansion from c_p to c_c, r = c_c - c_p (exact)."""
     b = _c(b_par, np.float64)
@@ -234,9 +245,11 @@ def start_offset(l: int) -> int:
 class Tree:
     """Oracle tree and interaction lists (Sec. 2 and Sec. 3.2, readings T1-T7,
     theta-criterion lists).  src/tgt are complex arrays; tgt None means the
-    evaluation points are the sources."""
+    evaluation points are the sources.  swap=True applies the leaf-level
+    swapped criterion: finest-level strong pairs that pass it become M2P
+    (target box larger) or P2L (source box larger) instead of P2P."""
 
-    def __init__(self, src, L, theta=0.5, tgt=None):
+    def __init__(self, src, L, theta=0.5, tgt=None, swap=False):
         lib = _load()
         self._s = _c(src, np.float64)
         self._t = None if tgt is None else _c(tgt, np.float64)
@@ -245,7 +258,8 @@ class Tree:
         self.L = int(L)
         self.theta = float(theta)
         self._lib = lib
-        self._h = lib.orc_build(self.ns, _p(self._s), self.nt, _p(self._t), self.L, self.theta)
+        self.swap = bool(swap)
+        self._h = lib.orc_build(self.ns, _p(self._s), self.nt, _p(self._t), self.L, self.theta, int(self.swap))
         if not self._h:
             raise ValueError("oracle tree: invalid arguments (need 0 <= L, 4^L <= N)")
         L = self.L
@@ -264,13 +278,19 @@ class Tree:
             self.tstart = self.sstart
         self.weak = []
         self.strong = []
+
+        def get(l, which):
+            n = lib.orc_list_len(self._h, l, which)
+            off = np.zeros(4 ** l + 1, np.int64)
+            idx = np.zeros(max(n, 1), np.int32)
+            lib.orc_get_list(self._h, l, which, _p(off), _p(idx))
+            return off, idx[:n]
+
         for l in range(L + 1):
-            for strong, dst in ((0, self.weak), (1, self.strong)):
-                n = lib.orc_list_len(self._h, l, strong)
-                off = np.zeros(4 ** l + 1, np.int64)
-                idx = np.zeros(max(n, 1), np.int32)
-                lib.orc_get_list(self._h, l, strong, _p(off), _p(idx))
-                dst.append((off, idx[:n]))
+            self.weak.append(get(l, 0))
+            self.strong.append(get(l, 1))
+        self.m2p = get(L, 2)
+        self.p2l = get(L, 3)
 
     def __del__(self):
         h = getattr(self, "_h", None)

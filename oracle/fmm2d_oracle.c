@@ -221,6 +221,28 @@ void orc_l2l(int p, const double *b_par, double rx, double ry, double *b_child)
     }
 }
 
+/* P2L (Sec. 2, leaf-level swapped criterion): the sources' field expanded
+ * directly as a local expansion about c, valid for |z - c| < |x - c|:
+ *   LOG:      m log(z-x) = m Log(c-x) - sum_{l>=1} m/(l (x-c)^l) (z-c)^l
+ *   HARMONIC: m/(z-x)    = -sum_{l>=0} m/(x-c)^{l+1} (z-c)^l
+ * Accumulates into b. */
+void orc_p2l(int kernel, int p, double cx, double cy, int64_t n, const double *x,
+             const double *m, double *b_out)
+{
+    cplx *b = (cplx *)b_out;
+    for (int64_t j = 0; j < n; ++j) {
+        cplx d = (x[2 * j] - cx) + I * (x[2 * j + 1] - cy); /* x - c */
+        cplx mj = m[2 * j] + I * m[2 * j + 1];
+        cplx di = 1.0 / d, pw = 1;
+        if (kernel == ORC_KERNEL_LOG) {
+            b[0] += mj * clog((cx - x[2 * j]) + I * (cy - x[2 * j + 1]));
+            for (int l = 1; l <= p; ++l) { pw *= di; b[l] -= mj * pw / (double)l; }
+        } else {
+            for (int l = 0; l <= p; ++l) { pw *= di; b[l] -= mj * pw; }
+        }
+    }
+}
+
 /* Evaluate a multipole expansion at z (principal Log), and its derivative. */
 void orc_eval_multipole(int p, const double *a_in, double cx, double cy,
                         double zx, double zy, double *val, double *der)
@@ -285,6 +307,9 @@ typedef struct {
     double *rad;           /* [nboxes]                                      */
     int64_t *woff[ORC_MAXL + 1], *soff[ORC_MAXL + 1];
     int32_t *widx[ORC_MAXL + 1], *sidx[ORC_MAXL + 1];
+    int swap;              /* leaf-level swapped criterion in use            */
+    int64_t *moff, *poff;  /* finest level: M2P and P2L lists (CSR)          */
+    int32_t *midx, *pidx;
 } orc_tree;
 
 static int64_t box_off(int l) { return ((((int64_t)1) << (2 * l)) - 1) / 3; }
@@ -370,6 +395,18 @@ static int theta_weak(const double *cb, double rb, const double *cs, double rs, 
     return d > 0.0 && R + theta * r <= theta * d;
 }
 
+/* The criterion with the roles of the radii interchanged (Sec. 2, last
+ * paragraph on the passes): r + theta R <= theta d. */
+static int theta_swapped(const double *cb, double rb, const double *cs, double rs, double theta)
+{
+    double dx = cb[0] - cs[0];
+    double dy = cb[1] - cs[1];
+    double d = sqrt(dx * dx + dy * dy);
+    double R = rb >= rs ? rb : rs;
+    double r = rb >= rs ? rs : rb;
+    return d > 0.0 && r + theta * R <= theta * d;
+}
+
 typedef struct { int32_t *v; int64_t n, cap; } ivec;
 static void ipush(ivec *a, int32_t x)
 {
@@ -383,11 +420,11 @@ static void ipush(ivec *a, int32_t x)
 void orc_free(orc_tree *T);
 
 orc_tree *orc_build(int64_t ns, const double *src, int64_t nt, const double *tgt,
-                    int L, double theta)
+                    int L, double theta, int swap)
 {
     if (ns <= 0 || L < 0 || L > ORC_MAXL || nbox(L) > ns) return NULL;
     orc_tree *T = (orc_tree *)calloc(1, sizeof(orc_tree));
-    T->L = L; T->theta = theta; T->ns = ns; T->src = src;
+    T->L = L; T->theta = theta; T->ns = ns; T->src = src; T->swap = swap;
     T->nt = tgt ? nt : 0; T->tgt = tgt;
     int64_t nb = box_off(L + 1);
     T->perm = (int32_t *)malloc((size_t)ns * sizeof(int32_t));
@@ -447,6 +484,9 @@ orc_tree *orc_build(int64_t ns, const double *src, int64_t nt, const double *tgt
     T->widx[0] = (int32_t *)malloc(sizeof(int32_t));
     T->sidx[0] = (int32_t *)malloc(sizeof(int32_t));
     T->soff[0][0] = 0; T->soff[0][1] = 1; T->sidx[0][0] = 0;
+    ivec mv = {0, 0, 0}, pv = {0, 0, 0};
+    T->moff = (int64_t *)calloc((size_t)nbox(L) + 1, sizeof(int64_t));
+    T->poff = (int64_t *)calloc((size_t)nbox(L) + 1, sizeof(int64_t));
     for (int l = 1; l <= L; ++l) {
         int64_t nbl = nbox(l);
         ivec wv = {0, 0, 0}, sv = {0, 0, 0};
@@ -457,6 +497,7 @@ orc_tree *orc_build(int64_t ns, const double *src, int64_t nt, const double *tgt
         for (int64_t b = 0; b < nbl; ++b) {
             T->woff[l][b] = wv.n;
             T->soff[l][b] = sv.n;
+            if (l == L) { T->moff[b] = mv.n; T->poff[b] = pv.n; }
             int64_t q = b / 4;
             for (int64_t e = T->soff[l - 1][q]; e < T->soff[l - 1][q + 1]; ++e) {
                 int64_t s = T->sidx[l - 1][e];
@@ -464,6 +505,9 @@ orc_tree *orc_build(int64_t ns, const double *src, int64_t nt, const double *tgt
                     int64_t c = 4 * s + k;
                     if (c != b && theta_weak(C + 2 * b, Rr[b], C + 2 * c, Rr[c], theta))
                         ipush(&wv, (int32_t)c);
+                    else if (l == L && swap && c != b &&
+                             theta_swapped(C + 2 * b, Rr[b], C + 2 * c, Rr[c], theta))
+                        ipush(Rr[b] > Rr[c] ? &mv : &pv, (int32_t)c);
                     else
                         ipush(&sv, (int32_t)c);
                 }
@@ -471,9 +515,12 @@ orc_tree *orc_build(int64_t ns, const double *src, int64_t nt, const double *tgt
         }
         T->woff[l][nbl] = wv.n;
         T->soff[l][nbl] = sv.n;
+        if (l == L) { T->moff[nbl] = mv.n; T->poff[nbl] = pv.n; }
         T->widx[l] = wv.v ? wv.v : (int32_t *)malloc(sizeof(int32_t));
         T->sidx[l] = sv.v ? sv.v : (int32_t *)malloc(sizeof(int32_t));
     }
+    T->midx = mv.v ? mv.v : (int32_t *)malloc(sizeof(int32_t));
+    T->pidx = pv.v ? pv.v : (int32_t *)malloc(sizeof(int32_t));
     return T;
 }
 
@@ -485,20 +532,34 @@ void orc_free(orc_tree *T)
     for (int l = 0; l <= T->L; ++l) {
         free(T->woff[l]); free(T->soff[l]); free(T->widx[l]); free(T->sidx[l]);
     }
+    free(T->moff); free(T->poff); free(T->midx); free(T->pidx);
     free(T);
 }
 
 /* Accessors for the Python wrapper. */
 int orc_levels_of(const orc_tree *T) { return T->L; }
-int64_t orc_list_len(const orc_tree *T, int l, int strong)
+/* which: 0 weak, 1 strong (P2P at the finest level), 2 M2P, 3 P2L (the last
+ * two exist at the finest level only). */
+static void list_of(const orc_tree *T, int l, int which, const int64_t **o, const int32_t **v)
 {
-    return strong ? T->soff[l][nbox(l)] : T->woff[l][nbox(l)];
+    switch (which) {
+    case 0: *o = T->woff[l]; *v = T->widx[l]; break;
+    case 1: *o = T->soff[l]; *v = T->sidx[l]; break;
+    case 2: *o = T->moff; *v = T->midx; break;
+    default: *o = T->poff; *v = T->pidx; break;
+    }
 }
-void orc_get_list(const orc_tree *T, int l, int strong, int64_t *off, int32_t *idx)
+int64_t orc_list_len(const orc_tree *T, int l, int which)
+{
+    const int64_t *o; const int32_t *v;
+    list_of(T, l, which, &o, &v);
+    return o[nbox(l)];
+}
+void orc_get_list(const orc_tree *T, int l, int which, int64_t *off, int32_t *idx)
 {
     int64_t nbl = nbox(l);
-    const int64_t *o = strong ? T->soff[l] : T->woff[l];
-    const int32_t *v = strong ? T->sidx[l] : T->widx[l];
+    const int64_t *o; const int32_t *v;
+    list_of(T, l, which, &o, &v);
     memcpy(off, o, (size_t)(nbl + 1) * sizeof(int64_t));
     memcpy(idx, v, (size_t)o[nbl] * sizeof(int32_t));
 }
@@ -582,7 +643,26 @@ int orc_eval(const orc_tree *T, const double *m, int kernel, int p,
                     T->cen[2 * g + 1] - T->cen[2 * q + 1], B + 2 * P1 * g);
         }
     }
-    /* L2P + P2P at the leaves */
+    /* P2L: sources of large boxes straight into the local expansions of the
+     * small leaves that pass the swapped criterion */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nleaf; ++t) {
+        int64_t g = lo + t;
+        for (int64_t e = T->poff[t]; e < T->poff[t + 1]; ++e) {
+            int64_t s = T->pidx[e];
+            int64_t n = sst[s + 1] - sst[s];
+            double *xs = (double *)malloc((size_t)(2 * n + 1) * sizeof(double));
+            double *ms = (double *)malloc((size_t)(2 * n + 1) * sizeof(double));
+            for (int64_t k = 0; k < n; ++k) {
+                int32_t j = T->perm[sst[s] + k];
+                xs[2 * k] = T->src[2 * j]; xs[2 * k + 1] = T->src[2 * j + 1];
+                ms[2 * k] = m[2 * j]; ms[2 * k + 1] = m[2 * j + 1];
+            }
+            orc_p2l(kernel, p, T->cen[2 * g], T->cen[2 * g + 1], n, xs, ms, B + 2 * P1 * g);
+            free(xs); free(ms);
+        }
+    }
+    /* L2P + M2P + P2P at the leaves */
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nleaf; ++t) {
         int64_t g = lo + t;
@@ -592,6 +672,13 @@ int orc_eval(const orc_tree *T, const double *m, int kernel, int p,
             double v[2], d[2];
             orc_eval_local(p, B + 2 * P1 * g, T->cen[2 * g], T->cen[2 * g + 1], yx, yy, v, d);
             cplx fv = v[0] + I * v[1], fd = d[0] + I * d[1];
+            /* M2P: multipoles of small leaves evaluated at this target */
+            for (int64_t e = T->moff[t]; e < T->moff[t + 1]; ++e) {
+                int64_t gs = lo + T->midx[e];
+                orc_eval_multipole(p, A + 2 * P1 * gs, T->cen[2 * gs], T->cen[2 * gs + 1], yx, yy, v, d);
+                fv += v[0] + I * v[1];
+                fd += d[0] + I * d[1];
+            }
             cplx nv = 0, nd = 0;
             for (int64_t e = T->soff[L][t]; e < T->soff[L][t + 1]; ++e) {
                 int64_t s = T->sidx[L][e];
@@ -673,8 +760,15 @@ int orc_direct_branch(const orc_tree *T, const double *m, const int64_t *tsel,
                     lev = l;
             }
             double ref = 0.0;
+            int mode = 0; /* 0 P2P or M2L at lev, 1 M2P (reference Arg(y - c_s)), 2 P2L (Arg(c_t - x)) */
             if (lev < 0) {
-                if (!in_sorted(T->sidx[L] + T->soff[L][t], T->soff[L][t + 1] - T->soff[L][t], (int32_t)s))
+                if (in_sorted(T->midx + T->moff[t], T->moff[t + 1] - T->moff[t], (int32_t)s)) {
+                    int64_t gs = box_off(L) + s;
+                    ref = atan2(yy - T->cen[2 * gs + 1], yx - T->cen[2 * gs]);
+                    mode = 1;
+                } else if (in_sorted(T->pidx + T->poff[t], T->poff[t + 1] - T->poff[t], (int32_t)s)) {
+                    mode = 2;
+                } else if (!in_sorted(T->sidx[L] + T->soff[L][t], T->soff[L][t + 1] - T->soff[L][t], (int32_t)s))
                     ++bad; /* not covered: lists are broken */
             } else {
                 int sh = 2 * (L - lev);
@@ -688,7 +782,11 @@ int orc_direct_branch(const orc_tree *T, const double *m, const int64_t *tsel,
                 cplx w = (yx - xx) + I * (yy - xy);
                 double lr = log(cabs(w));
                 double ar = carg(w);
-                if (lev >= 0) {
+                if (mode == 2) {
+                    int64_t gt = box_off(L) + t;
+                    ref = atan2(T->cen[2 * gt + 1] - xy, T->cen[2 * gt] - xx);
+                }
+                if (lev >= 0 || mode != 0) {
                     double dlt = ar - ref;
                     while (dlt > pi) dlt -= 2 * pi;
                     while (dlt <= -pi) dlt += 2 * pi;

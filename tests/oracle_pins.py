@@ -464,7 +464,94 @@ def pin_fmm_lattice_ties(orc):
         assert _rel(d, rd) < 1e-10, _rel(d, rd)
 
 
+def pin_p2l_near_field(orc):
+    """P2L of sources outside the disc |z - c| <= rT, evaluated inside it,
+    equals the direct sum within the truncated-series bound: with
+    q = rT / min|x - c|, the harmonic tail is at most sum|m| q^(p+1) /
+    (min|x-c| (1-q)) and the log tail sum|m| q^(p+1) / ((p+1)(1-q))."""
+    x, m = _cluster(13, n=25, c=0.8 + 0.7j, rad=0.1)
+    c, rT = 0.3 + 0.2j, 0.1
+    dmin = float(np.min(np.abs(x - c)))
+    q = rT / dmin
+    am = float(np.sum(np.abs(m)))
+    zs = c + rT * np.exp(1j * np.linspace(0.3, 6.0, 7))
+    for p in (5, 11, 19):
+        bh = orc.p2l(orc.KERNEL_HARMONIC, p, c, x, m)
+        bl = orc.p2l(orc.KERNEL_LOG, p, c, x, m)
+        for z in zs:
+            vh, _ = orc.eval_local(p, bh, c, z)
+            ref_d = np.sum(m / (z - x))
+            assert abs(vh - ref_d) <= 1.01 * am * q ** (p + 1) / (dmin * (1 - q)) + 1e-14 * abs(ref_d)
+            vl, dl = orc.eval_local(p, bl, c, z)
+            ref_p = np.sum(m * np.log(z - x))
+            assert abs(vl - ref_p) <= 1.01 * am * q ** (p + 1) / ((p + 1) * (1 - q)) + 1e-13 * abs(ref_p)
+            assert abs(dl - ref_d) <= 1.01 * am * (p + 2) * q ** (p + 1) / (dmin * (1 - q) ** 2) + 1e-13 * abs(ref_d)
+
+
+def pin_swap_lists(orc):
+    """Leaf-level swapped criterion: M2P and P2L pairs pass r + theta R <= theta d,
+    M2P has the larger target box, the two lists are mirror images, P2P pairs
+    fail both criteria, and every leaf pair is still handled exactly once."""
+    for dist, n, L in (("clusters", 4000, 4), ("spiral", 3000, 3)):
+        src = workloads.points(dist, n, 53)
+        T = orc.Tree(src, L, swap=True)
+        cen = T.centre[T.boxes(L)]
+        rad = T.radius[T.boxes(L)]
+        moff, midx = T.m2p
+        poff, pidx = T.p2l
+        soff, sidx = T.strong[L]
+        M = set()
+        P = set()
+        cov = np.zeros((4 ** L, 4 ** L), np.int64)
+        for b in range(4 ** L):
+            for s in midx[moff[b]:moff[b + 1]]:
+                d = abs(cen[b] - cen[s])
+                assert rad[b] > rad[s] and min(rad[b], rad[s]) + 0.5 * max(rad[b], rad[s]) <= 0.5 * d
+                M.add((b, int(s)))
+                cov[b, s] += 1
+            for s in pidx[poff[b]:poff[b + 1]]:
+                d = abs(cen[b] - cen[s])
+                assert rad[b] < rad[s] and min(rad[b], rad[s]) + 0.5 * max(rad[b], rad[s]) <= 0.5 * d
+                P.add((b, int(s)))
+                cov[b, s] += 1
+            for s in sidx[soff[b]:soff[b + 1]]:
+                d = abs(cen[b] - cen[s])
+                assert s == b or not (min(rad[b], rad[s]) + 0.5 * max(rad[b], rad[s]) <= 0.5 * d)
+                cov[b, s] += 1
+        assert len(M) > 0, "no swapped pair exercised"
+        assert M == {(s, b) for (b, s) in P}
+        for l in range(1, L + 1):
+            woff, widx = T.weak[l]
+            sh = 2 * (L - l)
+            for b in range(4 ** l):
+                for s in widx[woff[b]:woff[b + 1]]:
+                    cov[b << sh:(b + 1) << sh, s << sh:(s + 1) << sh] += 1
+        assert np.all(cov == 1)
+
+
+def pin_fmm_swap_converges(orc):
+    """With the swapped criterion the FMM still converges geometrically to the
+    direct sum (Phi against the branch-consistent sum, which follows Arg(y - c_s)
+    for M2P pairs and Arg(c_t - x) for P2L pairs)."""
+    src = workloads.points("clusters", 3000, 54)
+    m = workloads.strengths(3000, 55)
+    T = orc.Tree(src, 3, swap=True)
+    assert len(T.m2p[1]) > 0
+    _, rd = orc.direct(src, m)
+    sel = np.arange(0, 3000, 3)
+    rp = T.direct_branch(m, sel)
+    last = None
+    for p in (6, 12, 18, 24):
+        ph, dh = T.eval(m, p, orc.KERNEL_LOG)
+        _, dh2 = T.eval(m, p, orc.KERNEL_HARMONIC)
+        e = max(_rel(dh, rd), _rel(dh2, rd), _rel(ph[sel], rp))
+        if last is not None:
+            assert e < last * 0.2, (p, e, last)
+        last = e
+    assert last < 1e-8
+
+
 ALL_PINS = [pin_level_rule, pin_direct_roots_of_unity, pin_direct_bruteforce, pin_p2m_far_field,
             pin_m2m_exact, pin_l2l_exact, pin_m2l_closed_forms, pin_m2l_convergence, pin_tree_hand,
             pin_tree_invariants, pin_tree_targets_on_pivot, pin_lists, pin_fmm_L0_is_direct,
-            pin_fmm_theta_small_is_direct, pin_fmm_converges, pin_fmm_lattice_ties, pin_operating_point, pin_branch]
+            pin_fmm_theta_small_is_direct, pin_fmm_converges, pin_fmm_lattice_ties, pin_p2l_near_field, pin_swap_lists, pin_fmm_swap_converges, pin_operating_point, pin_branch]

@@ -37,6 +37,11 @@ MUTATIONS = [
     ("p2p coincident rule", "orc_eval", "if (xx == yx && xy == yy) continue;\n                    cplx w = (yx - xx) + I * (yy - xy);\n                    cplx mj",
      "if (xx == yx) continue;\n                    cplx w = (yx - xx) + I * (yy - xy);\n                    cplx mj"),
     ("direct sum drops imaginary part of m", "orc_direct", "cplx mj = m[2 * j] + I * m[2 * j + 1];", "cplx mj = m[2 * j];"),
+    ("p2l log power sign", "orc_p2l", "b[l] -= mj * pw / (double)l;", "b[l] += mj * pw / (double)l;"),
+    ("p2l harmonic power", "orc_p2l", "for (int l = 0; l <= p; ++l) { pw *= di; b[l] -= mj * pw; }",
+     "for (int l = 0; l <= p; ++l) { b[l] -= mj * pw; pw *= di; }"),
+    ("swap m2p/p2l roles", "orc_build", "ipush(Rr[b] > Rr[c] ? &mv : &pv, (int32_t)c);", "ipush(Rr[b] > Rr[c] ? &pv : &mv, (int32_t)c);"),
+    ("swapped test uses theta on r", "theta_swapped", "return d > 0.0 && r + theta * R <= theta * d;", "return d > 0.0 && theta * r + R <= theta * d;"),
     ("level rule off by one", "orc_nlevels", "while (lhs < (__int128)5 * n)", "while (lhs <= (__int128)5 * n)"),
 ]
 
