@@ -42,7 +42,7 @@ def l2p_flops_per_target(kernel: str, p: int) -> float:
 def run_path(f, fmm2d, src, m, kernel, p, precision, porder, steps, warmup):
     import torch
     opts = fmm2d.make_opts(p=p, levels=-1, leaf_target=45, kernel=kernel, precision=precision,
-                           porder=porder, timing=True)
+                           porder=porder, timing=True, swap=True)
     out = None
     for _ in range(warmup):
         out = f.eval(src, m, opts=opts, check=True)
@@ -161,7 +161,8 @@ def main():
                                   "frac": a64 / PEAK["f64"]}},
         "speedup_vs_fp64": fp64["ms"] / head["ms"],
         "phases_ms": head["phases"],
-        "counts": {"m2l_pairs": st["n_weak"], "p2p_leaf_pairs": st["n_strong"], "p2p_pairs": pairs},
+        "counts": {"m2l_pairs": st["n_weak"], "p2p_leaf_pairs": st["n_strong"], "m2p_leaf_pairs": st["n_m2p"],
+                   "p2l_leaf_pairs": st["n_p2l"], "p2p_pairs": pairs},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK["f32"], "traffic": None,
                      "kernel": "k_p2p32 (near field + L2P)",

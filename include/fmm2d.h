@@ -68,6 +68,10 @@ extern "C" {
 /* ---- flags ------------------------------------------------------------ */
 #define FMM2D_FLAG_TIMING 1u        /* record per-phase device times (events) */
 #define FMM2D_FLAG_REQUIRE_MODEL 2u /* learned order without a model is an error */
+#define FMM2D_FLAG_LEAF_SWAP 4u     /* finest-level strong pairs that pass the theta-
+                                       criterion with the radii interchanged (Sec. 2)
+                                       are handled by M2P (larger target box) or P2L
+                                       (larger source box) instead of P2P */
 
 typedef struct fmm2d_opts {
     double theta;        /* theta-criterion parameter, in (0,1); Sec. 2 uses 1/2 */
@@ -163,8 +167,12 @@ typedef struct fmm2d_topology {
                                   offsets into weak_idx (absolute) */
     const int32_t *weak_idx;   /* weak (M2L) source boxes, ascending per box,
                                   as per-level box numbers */
-    const int32_t *strong_off; /* same layout for strong boxes */
+    const int32_t *strong_off; /* same layout for strong boxes (P2P at the finest level) */
     const int32_t *strong_idx;
+    const int32_t *m2p_off;    /* finest level only (4^L + 1 entries, from 0): M2P */
+    const int32_t *m2p_idx;    /*   source leaves (empty without FMM2D_FLAG_LEAF_SWAP) */
+    const int32_t *p2l_off;    /* finest level only: P2L source leaves */
+    const int32_t *p2l_idx;
     const double *mpole;   /* [nboxes][p+1] complex multipole coefficients */
     const double *local;   /* [nboxes][p+1] complex local coefficients */
     const uint8_t *porder; /* [n_weak_total] learned orders, or NULL */
@@ -176,12 +184,14 @@ int fmm2d_get_topology(fmm2d_handle *h, fmm2d_topology *out);
  * FMM2D_FLAG_TIMING (else -1). */
 enum {
     FMM2D_PH_TREE = 0, FMM2D_PH_LISTS, FMM2D_PH_P2M, FMM2D_PH_M2M,
-    FMM2D_PH_PORDER, FMM2D_PH_M2L, FMM2D_PH_L2L, FMM2D_PH_P2P, FMM2D_NPHASE
+    FMM2D_PH_PORDER, FMM2D_PH_M2L, FMM2D_PH_L2L, FMM2D_PH_P2L, FMM2D_PH_P2P, FMM2D_NPHASE
 };
 typedef struct fmm2d_stats {
     float ms[FMM2D_NPHASE];
     int64_t n_weak;      /* M2L pairs over all levels */
     int64_t n_strong;    /* P2P leaf pairs */
+    int64_t n_m2p;       /* M2P leaf pairs */
+    int64_t n_p2l;       /* P2L leaf pairs */
     int64_t n_p2p_pairs; /* point-point pair evaluations in P2P */
     int32_t status;      /* as fmm2d_sync */
     int32_t used_model;  /* 1 if the learned order was used */

@@ -18,6 +18,15 @@ static inline int64_t box_off(int l) { return ((((int64_t)1) << (2 * l)) - 1) / 
 static inline int64_t nbox(int l) { return ((int64_t)1) << (2 * l); }
 static inline int64_t start_off(int l) { return box_off(l) + l; }
 
+// Index of the calling wave in a 1-D grid of 64-wide waves.  readfirstlane
+// tells the compiler the value is wave-uniform, so everything derived from it
+// (loop bounds, list entries, source records) lives in scalar registers and is
+// fetched with scalar loads.
+__device__ __forceinline__ int32_t wave_index()
+{
+    return __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64));
+}
+
 __device__ __forceinline__ int64_t d_box_off(int l) { return ((((int64_t)1) << (2 * l)) - 1) / 3; }
 __device__ __forceinline__ int64_t d_start_off(int l) { return d_box_off(l) + l; }
 
@@ -48,6 +57,8 @@ struct fmm_layout {
     size_t wcnt, scnt;           // per-box list counts (current level)
     size_t woff, soff;           // per-level list offsets
     size_t widx, sidx;           // global list arrays
+    size_t mcnt, pcnt, moff, poff, midx, pidx; // finest-level M2P / P2L lists
+    int64_t leafcap;             // entries of each M2P / P2L array
     size_t lbsum;                // list scan block sums
     size_t srcs;                 // double4 sources in leaf order
     size_t tgts;                 // double2 targets in leaf order
@@ -74,6 +85,7 @@ struct fmm_tree_args {
     const fmm_layout *lay;
     int32_t *status;              // device status word
     int cap;
+    int swap;                     // leaf-level swapped criterion (P2L / M2P)
 };
 // Builds perm/tperm, per-level starts, centres, radii and lists; gathers the
 // sources (with strengths) and targets into leaf order.
@@ -88,11 +100,13 @@ struct fmm_eval_args {
     const fmm_layout *lay;
     const double *binom;          // [FMM_BN][FMM_BN] FP64
     int32_t cap;
+    int swap;
 };
 hipError_t fmm_p2m(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_m2m(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_l2l(const fmm_eval_args &a, hipStream_t st);
+hipError_t fmm_p2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_p2p_l2p(const fmm_eval_args &a, double *phi, double *dphi, hipStream_t st);
 
 hipError_t fmm_direct(int64_t ns, const double *src, const double *m, int64_t nt,

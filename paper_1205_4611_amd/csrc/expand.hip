@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) k_p2m(const double4 *__restrict__ srcs,
                                               int32_t nleaf)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int32_t b = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int32_t b = wave_index();
     if (b >= nleaf) return;
     const int32_t s0 = sst[b], s1 = sst[b + 1];
     const double cx = centre[2 * (int64_t)b], cy = centre[2 * (int64_t)b + 1];
@@ -91,6 +91,79 @@ __global__ void __launch_bounds__(256) k_p2m(const double4 *__restrict__ srcs,
                     if (k < p) out[k + 1] = make_double2(r, i);
                     if (k == 0) out[0] = make_double2(0.0, 0.0);
                 }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ P2L --
+// Leaf-level swapped criterion: sources of a larger box, outside the target
+// leaf's disc, go straight into its local expansion (added after L2L).  With
+// d = x - c and u = 1/d:
+//   LOG:      b_0 += m Log(c - x),   b_l -= m u^l / l      (l >= 1)
+//   HARMONIC: b_l -= m u^{l+1}                            (l >= 0)
+// One wave per leaf, one source per lane, wave reduction of the p+1 sums.
+template <int PM>
+__global__ void __launch_bounds__(256) k_p2l(const double4 *__restrict__ srcs,
+                                              const int32_t *__restrict__ sst,
+                                              const int32_t *__restrict__ poff,
+                                              const int32_t *__restrict__ pidx,
+                                              const double *__restrict__ centre,
+                                              double2 *__restrict__ B, int p, int kernel,
+                                              int32_t nleaf, int32_t lcap)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int32_t t = wave_index();
+    if (t >= nleaf) return;
+    const int32_t e0 = min(poff[t], lcap), e1 = min(poff[t + 1], lcap);
+    if (e0 >= e1) return;
+    const double cx = centre[2 * (int64_t)t], cy = centre[2 * (int64_t)t + 1];
+    const bool LOG = kernel == FMM2D_KERNEL_LOG;
+    double sr[PM + 1], si[PM + 1];
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) { sr[k] = 0.0; si[k] = 0.0; }
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t s = __builtin_amdgcn_readfirstlane(min(max(pidx[e], 0), nleaf - 1));
+        const int32_t j0 = sst[s], j1 = sst[s + 1];
+        for (int32_t j = j0 + lane; j < j1; j += WAVE) {
+            const double4 q = srcs[j];
+            const double2 u = cinv(make_double2(q.x - cx, q.y - cy));
+            double2 pw = make_double2(q.z, q.w);
+            if (LOG) {
+                const double lx = cx - q.x, ly = cy - q.y; // Log(c - x), formed as written
+                const double2 lg = make_double2(0.5 * log(lx * lx + ly * ly), atan2(ly, lx));
+                const double2 t0 = cmul(pw, lg);
+                sr[0] += t0.x;
+                si[0] += t0.y;
+            }
+#pragma unroll
+            for (int k = 0; k <= PM; ++k) {
+                if (k <= p) {
+                    if (LOG) {
+                        if (k >= 1) {
+                            pw = cmul(pw, u);
+                            sr[k] -= pw.x / k;
+                            si[k] -= pw.y / k;
+                        }
+                    } else {
+                        pw = cmul(pw, u);
+                        sr[k] -= pw.x;
+                        si[k] -= pw.y;
+                    }
+                }
+            }
+        }
+    }
+    double2 *out = B + (int64_t)t * (p + 1);
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) {
+        if (k <= p) {
+            const double r = wave_sum(sr[k]), i = wave_sum(si[k]);
+            if (lane == 0) {
+                double2 o = out[k];
+                o.x += r;
+                o.y += i;
+                out[k] = o;
             }
         }
     }
@@ -193,27 +266,36 @@ __device__ __forceinline__ double2 clog_principal(double2 z)
     return make_double2(0.5 * log(z.x * z.x + z.y * z.y), atan2(z.y, z.x));
 }
 
-// FP64: one wave per target box, 8 weak pairs per MFMA column tile.
+#define M2L_HEAVY 256 // boxes with more weak pairs get an 8-wave workgroup
+#define M2L_WAVES 8
+
+__device__ __forceinline__ int32_t m2l_range(const m2l_args &a, int64_t g, int &l, int32_t &e0, int32_t &e1)
+{
+    l = level_of(g, a.L);
+    const int32_t b = (int32_t)(g - d_box_off(l));
+    const int64_t so = d_start_off(l);
+    e0 = min(a.woff[so + b], a.cap);
+    e1 = min(a.woff[so + b + 1], a.cap);
+    return e1 - e0;
+}
+
+// FP64 contraction for the chunks c = w, w + nw, ... of 8 weak pairs of box g.
 // Lane layout of v_mfma_f64_16x16x4f64: A operand lane i holds A[i%16][i/16],
-// B operand lane i holds B[i/16][i%16], accumulator lane i holds rows
-// 4(i/16)+j (j = 0..3) of column i%16.
+// B operand lane i holds B[i/16][i%16], accumulator element j of lane i holds
+// row 4j + i/16 of column i%16 (the FP64 instruction interleaves its rows).
+// On return acc[mt][j] holds, summed over this lane's pairs, the re (even
+// column) or im (odd column) part of b_l, l = 16 mt + 4 j + kq.
 template <int MT, int KS>
-__global__ void __launch_bounds__(256) k_m2l64(m2l_args a)
+__device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, int32_t e0, int32_t e1, int w,
+                                          int nw, double (&acc)[MT][4])
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t g = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    if (g >= a.nb) return;
-    const int l = level_of(g, a.L);
     const int64_t bo = d_box_off(l);
-    const int32_t b = (int32_t)(g - bo);
-    const int64_t so = d_start_off(l);
-    const int32_t e0 = min(a.woff[so + b], a.cap), e1 = min(a.woff[so + b + 1], a.cap);
     const int p = a.p, P1 = p + 1;
     const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
     const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
     const double2 cT = make_double2(a.centre[2 * g], a.centre[2 * g + 1]);
     const bool LOG = a.kernel == FMM2D_KERNEL_LOG;
-
     double Sop[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -222,13 +304,12 @@ __global__ void __launch_bounds__(256) k_m2l64(m2l_args a)
             const int row = 16 * mt + col, kk = 4 * ks + kq;
             Sop[mt][ks] = (row <= p && kk < p) ? a.binom[(row + kk) * FMM_BN + row] : 0.0;
         }
-    double acc[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
 
-    for (int32_t e = e0; e < e1; e += 8) {
+    for (int32_t e = e0 + 8 * w; e < e1; e += 8 * nw) {
         const int32_t pe = e + ps;
         const bool valid = pe < e1;
         int32_t sb = valid ? a.widx[pe] : 0;
@@ -292,8 +373,7 @@ __global__ void __launch_bounds__(256) k_m2l64(m2l_args a)
             acc[0][0] += comp ? t.y : t.x;
         }
     }
-    // sum over the 8 pairs of a tile (lane bits 1..3), write b
-    double2 *Bt = a.B + g * P1;
+    // sum over the 8 pairs of a tile (lane bits 1..3)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -302,9 +382,58 @@ __global__ void __launch_bounds__(256) k_m2l64(m2l_args a)
             v += __shfl_xor(v, 2, WAVE);
             v += __shfl_xor(v, 4, WAVE);
             v += __shfl_xor(v, 8, WAVE);
-            const int row = 16 * mt + 4 * j + kq;
-            if (ps == 0 && row <= p) reinterpret_cast<double *>(Bt + row)[comp] = v;
+            acc[mt][j] = v;
         }
+}
+
+template <int MT, int KS, bool HEAVY>
+__global__ void __launch_bounds__(HEAVY ? 64 * M2L_WAVES : 256) k_m2l64(m2l_args a)
+{
+    __shared__ double part[HEAVY ? M2L_WAVES : 1][MT * 16][2];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
+    const int P1 = a.p + 1;
+    if (!HEAVY) {
+        const int64_t g = wave_index();
+        if (g >= a.nb) return;
+        int l;
+        int32_t e0, e1;
+        if (m2l_range(a, g, l, e0, e1) > M2L_HEAVY) return;
+        double acc[MT][4];
+        m2l64_acc<MT, KS>(a, g, l, e0, e1, 0, 1, acc);
+        double2 *Bt = a.B + g * P1;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = 16 * mt + 4 * j + kq;
+                if (ps == 0 && row <= a.p) reinterpret_cast<double *>(Bt + row)[comp] = acc[mt][j];
+            }
+    } else {
+        const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+        for (int64_t g = blockIdx.x; g < a.nb; g += gridDim.x) {
+            int l;
+            int32_t e0, e1;
+            if (m2l_range(a, g, l, e0, e1) <= M2L_HEAVY) continue;
+            double acc[MT][4];
+            m2l64_acc<MT, KS>(a, g, l, e0, e1, w, M2L_WAVES, acc);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (ps == 0) part[w][16 * mt + 4 * j + kq][comp] = acc[mt][j];
+            __syncthreads();
+            if (w == 0) {
+                double2 *Bt = a.B + g * P1;
+                for (int k = lane; k < 2 * P1; k += WAVE) {
+                    double v = 0.0;
+                    for (int q = 0; q < M2L_WAVES; ++q) v += part[q][k >> 1][k & 1];
+                    reinterpret_cast<double *>(Bt)[k] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // FP32 (mixed precision): the same contraction on v_mfma_f32_16x16x4f32 with
@@ -325,17 +454,14 @@ __device__ __forceinline__ double scale_floor(const double *radius)
     return fmax(radius[0] * 0x1p-40, 1e-300);
 }
 
+// Accumulator layout of v_mfma_f32_16x16x4f32: element j of lane i holds row
+// 4 (i/16) + j of column i%16.  acc0 collects the FP64 a_0 Log term of row 0.
 template <int MT, int KS>
-__global__ void __launch_bounds__(256) k_m2l32(m2l_args a)
+__device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, int32_t e0, int32_t e1, int w,
+                                          int nw, float (&acc)[MT][4], double &acc0)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t g = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    if (g >= a.nb) return;
-    const int l = level_of(g, a.L);
     const int64_t bo = d_box_off(l);
-    const int32_t b = (int32_t)(g - bo);
-    const int64_t so = d_start_off(l);
-    const int32_t e0 = min(a.woff[so + b], a.cap), e1 = min(a.woff[so + b + 1], a.cap);
     const int p = a.p, P1 = p + 1;
     const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
     const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
@@ -343,7 +469,6 @@ __global__ void __launch_bounds__(256) k_m2l32(m2l_args a)
     const double rmin = scale_floor(a.radius);
     const double sT = scale_radius(a.radius[g], rmin);
     const bool LOG = a.kernel == FMM2D_KERNEL_LOG;
-
     float Sop[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -352,14 +477,12 @@ __global__ void __launch_bounds__(256) k_m2l32(m2l_args a)
             const int row = 16 * mt + col, kk = 4 * ks + kq;
             Sop[mt][ks] = (row <= p && kk < p) ? (float)a.binom[(row + kk) * FMM_BN + row] : 0.0f;
         }
-    float acc[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0f;
-    double acc0 = 0.0; // FP64 a_0 Log term of row 0
-
-    for (int32_t e = e0; e < e1; e += 8) {
+    acc0 = 0.0;
+    for (int32_t e = e0 + 8 * w; e < e1; e += 8 * nw) {
         const int32_t pe = e + ps;
         const bool valid = pe < e1;
         int32_t sb = valid ? a.widx[pe] : 0;
@@ -428,8 +551,6 @@ __global__ void __launch_bounds__(256) k_m2l32(m2l_args a)
             acc0 += comp ? t.y : t.x;
         }
     }
-    double2 *Bt = a.B + g * P1;
-    const double isT = 1.0 / sT;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -438,20 +559,79 @@ __global__ void __launch_bounds__(256) k_m2l32(m2l_args a)
             vv += __shfl_xor(vv, 2, WAVE);
             vv += __shfl_xor(vv, 4, WAVE);
             vv += __shfl_xor(vv, 8, WAVE);
-            const int row = 16 * mt + 4 * kq + j;
-            double d = (double)vv;
-            if (mt == 0 && j == 0) {
-                double x = acc0;
-                x += __shfl_xor(x, 2, WAVE);
-                x += __shfl_xor(x, 4, WAVE);
-                x += __shfl_xor(x, 8, WAVE);
-                if (kq == 0) d += x;
-            }
-            // unscale: b_l = bhat_l / sigma_T^l in FP64, one factor at a time
-            // so that no intermediate power over- or underflows
-            for (int q = 0; q < row; ++q) d *= isT;
-            if (ps == 0 && row <= p) reinterpret_cast<double *>(Bt + row)[comp] = d;
+            acc[mt][j] = vv;
         }
+    acc0 += __shfl_xor(acc0, 2, WAVE);
+    acc0 += __shfl_xor(acc0, 4, WAVE);
+    acc0 += __shfl_xor(acc0, 8, WAVE);
+}
+
+// b_l = bhat_l / sigma_T^l in FP64, one factor at a time so that no
+// intermediate power over- or underflows.
+__device__ __forceinline__ double m2l32_unscale(double v, int row, double isT)
+{
+    for (int q = 0; q < row; ++q) v *= isT;
+    return v;
+}
+
+template <int MT, int KS, bool HEAVY>
+__global__ void __launch_bounds__(HEAVY ? 64 * M2L_WAVES : 256) k_m2l32(m2l_args a)
+{
+    __shared__ double part[HEAVY ? M2L_WAVES : 1][MT * 16][2];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
+    const int P1 = a.p + 1;
+    if (!HEAVY) {
+        const int64_t g = wave_index();
+        if (g >= a.nb) return;
+        int l;
+        int32_t e0, e1;
+        if (m2l_range(a, g, l, e0, e1) > M2L_HEAVY) return;
+        float acc[MT][4];
+        double acc0;
+        m2l32_acc<MT, KS>(a, g, l, e0, e1, 0, 1, acc, acc0);
+        const double isT = 1.0 / scale_radius(a.radius[g], scale_floor(a.radius));
+        double2 *Bt = a.B + g * P1;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = 16 * mt + 4 * kq + j;
+                double d = (double)acc[mt][j];
+                if (row == 0) d += acc0;
+                if (ps == 0 && row <= a.p) reinterpret_cast<double *>(Bt + row)[comp] = m2l32_unscale(d, row, isT);
+            }
+    } else {
+        const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+        for (int64_t g = blockIdx.x; g < a.nb; g += gridDim.x) {
+            int l;
+            int32_t e0, e1;
+            if (m2l_range(a, g, l, e0, e1) <= M2L_HEAVY) continue;
+            float acc[MT][4];
+            double acc0;
+            m2l32_acc<MT, KS>(a, g, l, e0, e1, w, M2L_WAVES, acc, acc0);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = 16 * mt + 4 * kq + j;
+                    double d = (double)acc[mt][j];
+                    if (row == 0) d += acc0;
+                    if (ps == 0) part[w][row][comp] = d;
+                }
+            __syncthreads();
+            if (w == 0) {
+                const double isT = 1.0 / scale_radius(a.radius[g], scale_floor(a.radius));
+                double2 *Bt = a.B + g * P1;
+                for (int k = lane; k < 2 * P1; k += WAVE) {
+                    double v = 0.0;
+                    for (int q = 0; q < M2L_WAVES; ++q) v += part[q][k >> 1][k & 1];
+                    reinterpret_cast<double *>(Bt)[k] = m2l32_unscale(v, k >> 1, isT);
+                }
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // FP32 radius-scaled copy of the multipoles: ahat_k = a_k / sigma^k.
@@ -494,6 +674,29 @@ hipError_t fmm_p2m(const fmm_eval_args &a, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int PM>
+static void launch_p2l(const fmm_eval_args &a, hipStream_t st)
+{
+    const fmm_layout &lay = *a.lay;
+    const int64_t nleaf = nbox(a.L);
+    const unsigned nblk = (unsigned)((nleaf + 3) / 4);
+    k_p2l<PM><<<nblk, 256, 0, st>>>(WSC(double4, lay.srcs), WSC(int32_t, lay.sstart) + start_off(a.L),
+                                    WSC(int32_t, lay.poff), WSC(int32_t, lay.pidx),
+                                    WSC(double, lay.centre) + 2 * box_off(a.L),
+                                    WSC(double2, lay.B) + box_off(a.L) * (a.p + 1), a.p, a.kernel,
+                                    (int32_t)nleaf, (int32_t)lay.leafcap);
+}
+
+hipError_t fmm_p2l(const fmm_eval_args &a, hipStream_t st)
+{
+    if (!a.swap) return hipSuccess;
+    if (a.p <= 20) launch_p2l<20>(a, st);
+    else if (a.p <= 32) launch_p2l<32>(a, st);
+    else if (a.p <= 44) launch_p2l<44>(a, st);
+    else launch_p2l<64>(a, st);
+    return hipGetLastError();
+}
+
 hipError_t fmm_m2m(const fmm_eval_args &a, hipStream_t st)
 {
     const fmm_layout &lay = *a.lay;
@@ -520,8 +723,14 @@ template <int MT, int KS>
 static void launch_m2l(const m2l_args &m, bool mixed, hipStream_t st)
 {
     const unsigned nblk = (unsigned)((m.nb + 3) / 4);
-    if (mixed) k_m2l32<MT, KS><<<nblk, 256, 0, st>>>(m);
-    else k_m2l64<MT, KS><<<nblk, 256, 0, st>>>(m);
+    const unsigned nheavy = (unsigned)(m.nb < 1024 ? m.nb : 1024);
+    if (mixed) {
+        k_m2l32<MT, KS, false><<<nblk, 256, 0, st>>>(m);
+        k_m2l32<MT, KS, true><<<nheavy, 64 * M2L_WAVES, 0, st>>>(m);
+    } else {
+        k_m2l64<MT, KS, false><<<nblk, 256, 0, st>>>(m);
+        k_m2l64<MT, KS, true><<<nheavy, 64 * M2L_WAVES, 0, st>>>(m);
+    }
 }
 
 hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st)

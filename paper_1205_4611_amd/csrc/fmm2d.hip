@@ -123,6 +123,13 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->soff = take(4 * lay->nstart);
     lay->widx = take(4 * lay->listcap);
     lay->sidx = take(4 * lay->listcap);
+    lay->leafcap = (int64_t)cap * lay->nleaf + 4;
+    lay->mcnt = take(4 * lay->nleaf);
+    lay->pcnt = take(4 * lay->nleaf);
+    lay->moff = take(4 * (lay->nleaf + 1));
+    lay->poff = take(4 * (lay->nleaf + 1));
+    lay->midx = take(4 * lay->leafcap);
+    lay->pidx = take(4 * lay->leafcap);
     lay->lbsum = take(4 * (fmm_scan_blocks(lay->nleaf) + 2));
     lay->srcs = take(32 * ns);
     lay->tgts = take(16 * nt);
@@ -267,6 +274,7 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     fmm_tree_args ta;
     ta.ns = n_src; ta.nt = nt; ta.L = L; ta.theta = opts->theta;
     ta.src = src; ta.tgt = tgt; ta.ws = w; ta.lay = &lay; ta.status = h->d_status; ta.cap = cap;
+    ta.swap = (opts->flags & FMM2D_FLAG_LEAF_SWAP) != 0;
     HIPCHK(h, fmm_build_tree(ta, m, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_TREE], st));
     HIPCHK(h, fmm_build_lists(ta, st));
@@ -275,7 +283,7 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     fmm_eval_args ea;
     ea.L = L; ea.p = p; ea.kernel = (int)opts->kernel; ea.mixed = mixed;
     ea.ns = n_src; ea.nt = nt ? nt : n_src; ea.at_sources = nt == 0;
-    ea.ws = w; ea.lay = &lay; ea.binom = h->d_binom; ea.cap = cap;
+    ea.ws = w; ea.lay = &lay; ea.binom = h->d_binom; ea.cap = cap; ea.swap = ta.swap;
     HIPCHK(h, fmm_p2m(ea, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], st));
     HIPCHK(h, fmm_m2m(ea, st));
@@ -286,6 +294,8 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2L], st));
     HIPCHK(h, fmm_l2l(ea, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_L2L], st));
+    HIPCHK(h, fmm_p2l(ea, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2L], st));
     HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2P], st));
 
@@ -352,6 +362,10 @@ extern "C" int fmm2d_get_topology(fmm2d_handle *h, fmm2d_topology *t)
     t->weak_idx = reinterpret_cast<const int32_t *>(w + lay.widx);
     t->strong_off = reinterpret_cast<const int32_t *>(w + lay.soff);
     t->strong_idx = reinterpret_cast<const int32_t *>(w + lay.sidx);
+    t->m2p_off = reinterpret_cast<const int32_t *>(w + lay.moff);
+    t->m2p_idx = reinterpret_cast<const int32_t *>(w + lay.midx);
+    t->p2l_off = reinterpret_cast<const int32_t *>(w + lay.poff);
+    t->p2l_idx = reinterpret_cast<const int32_t *>(w + lay.pidx);
     t->mpole = reinterpret_cast<const double *>(w + lay.A);
     t->local = reinterpret_cast<const double *>(w + lay.B);
     t->porder = nullptr;
@@ -382,6 +396,15 @@ extern "C" int fmm2d_get_stats(fmm2d_handle *h, fmm2d_stats *s)
     HIPCHK(h, hipMemcpy(&send_prev, soff + start_off(L), 4, hipMemcpyDeviceToHost));
     s->n_weak = wend;
     s->n_strong = (int64_t)send - send_prev;
+    {
+        int32_t mend = 0, pend = 0;
+        HIPCHK(h, hipMemcpy(&mend, reinterpret_cast<const int32_t *>(h->ws + lay.moff) + nbox(L), 4,
+                            hipMemcpyDeviceToHost));
+        HIPCHK(h, hipMemcpy(&pend, reinterpret_cast<const int32_t *>(h->ws + lay.poff) + nbox(L), 4,
+                            hipMemcpyDeviceToHost));
+        s->n_m2p = mend;
+        s->n_p2l = pend;
+    }
     if (s->status == FMM2D_OK) {
         const int64_t nl = nbox(L);
         int32_t *so = (int32_t *)malloc(4 * (nl + 1));

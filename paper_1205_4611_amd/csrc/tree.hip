@@ -437,6 +437,18 @@ __device__ __forceinline__ bool theta_weak(double cbx, double cby, double rb, do
     return d > 0.0 && R + theta * r <= theta * d;
 }
 
+// The criterion with the radii interchanged (leaf-level swap): r + theta R <= theta d.
+__device__ __forceinline__ bool theta_swapped(double cbx, double cby, double rb, double csx,
+                                              double csy, double rs, double theta)
+{
+    const double dx = cbx - csx;
+    const double dy = cby - csy;
+    const double d = sqrt(dx * dx + dy * dy);
+    const double R = rb >= rs ? rb : rs;
+    const double r = rb >= rs ? rs : rb;
+    return d > 0.0 && r + theta * R <= theta * d;
+}
+
 struct list_args {
     const double *centre, *radius; // level l arrays (offset)
     const int32_t *psoff;          // level l-1 strong offsets (offset)
@@ -448,45 +460,96 @@ struct list_args {
     int32_t cap;
     double theta;
     int32_t *status;
+    int swap;                      // finest level with the swapped criterion
+    int32_t *mcnt, *pcnt;          // M2P / P2L counts (count pass)
+    const int32_t *moff, *poff;    // M2P / P2L offsets (fill pass)
+    int32_t *midx_out, *pidx_out;  // M2P / P2L lists (fill pass)
+    int32_t lcap;                  // capacity of the M2P / P2L arrays
 };
 
+// One wave per box: the lanes take the candidates (children 4s..4s+3 of the
+// parent's strong boxes, in ascending order) 64 at a time, test them in
+// parallel, and compact each class in order with ballots.  Classes: weak
+// (M2L), strong (next level; P2P at the finest), and at the finest level with
+// the swapped criterion M2P (this box larger) and P2L (candidate larger).
 template <bool FILL>
-__global__ void k_lists(list_args a)
+__global__ void __launch_bounds__(256) k_lists(list_args a)
 {
-    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int32_t b = wave_index();
     if (b >= a.nbl) return;
     const int32_t q = b >> 2;
     const int32_t e0 = min(a.psoff[q], a.cap), e1 = min(a.psoff[q + 1], a.cap);
+    const int32_t ncand = 4 * (e1 - e0);
     const double cbx = a.centre[2 * (int64_t)b], cby = a.centre[2 * (int64_t)b + 1];
     const double rb = a.radius[b];
-    int32_t nw = 0, nsg = 0;
-    int32_t wo = 0, so = 0, we = 0, se = 0;
+    int32_t wo = 0, so = 0, mo = 0, po = 0;
     if (FILL) {
-        wo = a.woff[b]; we = a.woff[b + 1];
-        so = a.soff[b]; se = a.soff[b + 1];
-        if (we > a.cap || se > a.cap) atomicOr(a.status, FMM_ST_LIST_OVERFLOW);
+        wo = a.woff[b];
+        so = a.soff[b];
+        bool over = a.woff[b + 1] > a.cap || a.soff[b + 1] > a.cap;
+        if (a.swap) {
+            mo = a.moff[b];
+            po = a.poff[b];
+            over = over || a.moff[b + 1] > a.lcap || a.poff[b + 1] > a.lcap;
+        }
+        if (lane == 0 && over) atomicOr(a.status, FMM_ST_LIST_OVERFLOW);
     }
-    for (int32_t e = e0; e < e1; ++e) {
-        int32_t s = a.sidx[e];
-        s = min(max(s, 0), (a.nbl >> 2) - 1);
-        for (int k = 0; k < 4; ++k) {
-            const int32_t c = 4 * s + k;
-            const bool weak = (c != b) && theta_weak(cbx, cby, rb, a.centre[2 * (int64_t)c],
-                                                     a.centre[2 * (int64_t)c + 1], a.radius[c],
-                                                     a.theta);
-            if (weak) {
-                if (FILL && wo + nw < a.cap) a.widx_out[wo + nw] = c;
-                ++nw;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+    int32_t nw = 0, nsg = 0, nm = 0, np = 0;
+    for (int32_t k0 = 0; k0 < ncand; k0 += WAVE) {
+        const int32_t k = k0 + lane;
+        const bool act = k < ncand;
+        int cls = 1; // 0 weak, 1 strong, 2 M2P, 3 P2L
+        int32_t c = 0;
+        if (act) {
+            int32_t s = a.sidx[e0 + (k >> 2)];
+            s = min(max(s, 0), (a.nbl >> 2) - 1);
+            c = 4 * s + (k & 3);
+            const double ccx = a.centre[2 * (int64_t)c], ccy = a.centre[2 * (int64_t)c + 1];
+            const double rc = a.radius[c];
+            if (c != b && theta_weak(cbx, cby, rb, ccx, ccy, rc, a.theta)) cls = 0;
+            else if (a.swap && c != b && theta_swapped(cbx, cby, rb, ccx, ccy, rc, a.theta))
+                cls = rb > rc ? 2 : 3;
+        }
+        const uint64_t mw = __ballot(act && cls == 0);
+        const uint64_t ms = __ballot(act && cls == 1);
+        const uint64_t mm = __ballot(act && cls == 2);
+        const uint64_t mp = __ballot(act && cls == 3);
+        if (FILL && act) {
+            if (cls == 0) {
+                const int32_t pos = wo + nw + __popcll(mw & lt);
+                if (pos < a.cap) a.widx_out[pos] = c;
+            } else if (cls == 1) {
+                const int32_t pos = so + nsg + __popcll(ms & lt);
+                if (pos < a.cap) a.sidx_out[pos] = c;
+            } else if (cls == 2) {
+                const int32_t pos = mo + nm + __popcll(mm & lt);
+                if (pos < a.lcap) a.midx_out[pos] = c;
             } else {
-                if (FILL && so + nsg < a.cap) a.sidx_out[so + nsg] = c;
-                ++nsg;
+                const int32_t pos = po + np + __popcll(mp & lt);
+                if (pos < a.lcap) a.pidx_out[pos] = c;
             }
         }
+        nw += __popcll(mw);
+        nsg += __popcll(ms);
+        nm += __popcll(mm);
+        np += __popcll(mp);
     }
-    if (!FILL) {
+    if (!FILL && lane == 0) {
         a.wcnt[b] = nw;
         a.scnt[b] = nsg;
+        if (a.swap) {
+            a.mcnt[b] = nm;
+            a.pcnt[b] = np;
+        }
     }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 __global__ void k_root(int32_t *sstep, int32_t ns, int32_t *tstep, int32_t nt)
@@ -659,6 +722,10 @@ hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st)
     int32_t *wcnt = WS(int32_t, lay.wcnt), *scnt = WS(int32_t, lay.scnt);
     int32_t *lbsum = WS(int32_t, lay.lbsum);
     k_lists_root<<<1, 1, 0, st>>>(woff, soff, sidx);
+    if (!a.swap) {
+        k_fill_i32<<<nblk256(nbox(L) + 1), 256, 0, st>>>(WS(int32_t, lay.moff), nbox(L) + 1, 0);
+        k_fill_i32<<<nblk256(nbox(L) + 1), 256, 0, st>>>(WS(int32_t, lay.poff), nbox(L) + 1, 0);
+    }
     for (int l = 1; l <= L; ++l) {
         list_args la;
         la.centre = centre + 2 * box_off(l);
@@ -673,12 +740,25 @@ hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st)
         la.cap = (int32_t)lay.listcap;
         la.theta = a.theta;
         la.status = a.status;
-        k_lists<false><<<nblk256(nbox(l)), 256, 0, st>>>(la);
+        la.swap = (l == L) && a.swap;
+        la.mcnt = WS(int32_t, lay.mcnt);
+        la.pcnt = WS(int32_t, lay.pcnt);
+        la.moff = WS(int32_t, lay.moff);
+        la.poff = WS(int32_t, lay.poff);
+        la.midx_out = WS(int32_t, lay.midx);
+        la.pidx_out = WS(int32_t, lay.pidx);
+        la.lcap = (int32_t)lay.leafcap;
+        const unsigned nwb = (unsigned)((nbox(l) + 3) / 4); // 4 waves (boxes) per block
+        k_lists<false><<<nwb, 256, 0, st>>>(la);
         CK(fmm_scan_i32(wcnt, woff + start_off(l), nbox(l), woff + start_off(l - 1) + nbox(l - 1),
                         lbsum, st));
         CK(fmm_scan_i32(scnt, soff + start_off(l), nbox(l), soff + start_off(l - 1) + nbox(l - 1),
                         lbsum, st));
-        k_lists<true><<<nblk256(nbox(l)), 256, 0, st>>>(la);
+        if (la.swap) {
+            CK(fmm_scan_i32(la.mcnt, WS(int32_t, lay.moff), nbox(l), nullptr, lbsum, st));
+            CK(fmm_scan_i32(la.pcnt, WS(int32_t, lay.poff), nbox(l), nullptr, lbsum, st));
+        }
+        k_lists<true><<<nwb, 256, 0, st>>>(la);
         CK(hipGetLastError());
     }
     return hipSuccess;

@@ -21,7 +21,8 @@ PRECISION = {"fp64": 0, "mixed": 1}
 PORDER = {"fixed": 0, "learned": 1}
 FLAG_TIMING = 1
 FLAG_REQUIRE_MODEL = 2
-PHASES = ("tree", "lists", "p2m", "m2m", "porder", "m2l", "l2l", "p2p")
+FLAG_LEAF_SWAP = 4
+PHASES = ("tree", "lists", "p2m", "m2m", "porder", "m2l", "l2l", "p2l", "p2p")
 
 #: every symbol include/fmm2d.h declares
 EXPORTS = ("fmm2d_default_opts", "fmm2d_create", "fmm2d_destroy", "fmm2d_last_error",
@@ -42,12 +43,14 @@ class Topology(ctypes.Structure):
                 ("n_tgt", ctypes.c_int64)] + [
         (n, ctypes.c_void_p) for n in ("perm", "tperm", "sstart", "tstart", "centre", "radius",
                                        "weak_off", "weak_idx", "strong_off", "strong_idx",
+                                       "m2p_off", "m2p_idx", "p2l_off", "p2l_idx",
                                        "mpole", "local", "porder")]
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_float * 8), ("n_weak", ctypes.c_int64),
-                ("n_strong", ctypes.c_int64), ("n_p2p_pairs", ctypes.c_int64),
+    _fields_ = [("ms", ctypes.c_float * 9), ("n_weak", ctypes.c_int64),
+                ("n_strong", ctypes.c_int64), ("n_m2p", ctypes.c_int64), ("n_p2l", ctypes.c_int64),
+                ("n_p2p_pairs", ctypes.c_int64),
                 ("status", ctypes.c_int32), ("used_model", ctypes.c_int32),
                 ("p_hist", ctypes.c_int64 * 65)]
 
@@ -103,7 +106,7 @@ def nlevels(n: int, nd: int) -> int:
 
 def make_opts(theta=0.5, tol=1e-6, p=0, levels=-1, leaf_target=45, kernel="log",
               precision="fp64", porder="fixed", timing=False, require_model=False,
-              list_cap=0) -> Opts:
+              list_cap=0, swap=False) -> Opts:
     o = Opts()
     load().fmm2d_default_opts(ctypes.byref(o))
     o.theta = float(theta)
@@ -114,7 +117,8 @@ def make_opts(theta=0.5, tol=1e-6, p=0, levels=-1, leaf_target=45, kernel="log",
     o.kernel = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.porder = PORDER[porder] if isinstance(porder, str) else int(porder)
-    o.flags = (FLAG_TIMING if timing else 0) | (FLAG_REQUIRE_MODEL if require_model else 0)
+    o.flags = ((FLAG_TIMING if timing else 0) | (FLAG_REQUIRE_MODEL if require_model else 0)
+               | (FLAG_LEAF_SWAP if swap else 0))
     o.list_cap = int(list_cap)
     return o
 
@@ -242,7 +246,8 @@ class FMM2D:
         if rc != OK:
             raise self._err(rc)
         return {"ms": {k: float(st.ms[i]) for i, k in enumerate(PHASES)}, "n_weak": st.n_weak,
-                "n_strong": st.n_strong, "n_p2p_pairs": st.n_p2p_pairs, "status": st.status,
+                "n_strong": st.n_strong, "n_m2p": st.n_m2p, "n_p2l": st.n_p2l,
+                "n_p2p_pairs": st.n_p2p_pairs, "status": st.status,
                 "used_model": st.used_model, "p_hist": list(st.p_hist)}
 
     def topology(self, coeffs: bool = False) -> dict:
@@ -271,7 +276,12 @@ class FMM2D:
         so_L = nb - 4 ** L + L  # start offset of level L
         nw = int(woff[so_L + 4 ** L])
         nsg = int(soff[so_L + 4 ** L])
+        nl = 4 ** L
+        moff = dev(tp.m2p_off, nl + 1, np.int32)
+        poff = dev(tp.p2l_off, nl + 1, np.int32)
         out = {
+            "m2p_off": moff, "m2p_idx": dev(tp.m2p_idx, int(moff[-1]), np.int32),
+            "p2l_off": poff, "p2l_idx": dev(tp.p2l_idx, int(poff[-1]), np.int32),
             "levels": L, "p": p,
             "perm": dev(tp.perm, tp.n_src, np.int32),
             "tperm": dev(tp.tperm, tp.n_tgt, np.int32),

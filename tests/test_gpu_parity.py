@@ -105,29 +105,38 @@ def _compare_topology(orc, top, T, L):
             ro, ri = lists[l]
             assert np.array_equal(off - off[0], ro), (key, l)
             assert np.array_equal(idx, ri), (key, l)
+    for key, lst in (("m2p", T.m2p), ("p2l", T.p2l)):
+        off = top[key + "_off"].astype(np.int64)
+        assert np.array_equal(off, lst[0]), key
+        assert np.array_equal(top[key + "_idx"][:off[-1]], lst[1]), key
 
 
+@pytest.mark.parametrize("swap", [False, True])
 @pytest.mark.parametrize("name", [c[0] for c in TREE_CASES] + ["lattice_ties"])
-def test_tree_and_lists_bitexact(fmm, orc, name):
+def test_tree_and_lists_bitexact(fmm, orc, name, swap):
     src, tgt, L = _case(name)
     m = workloads.strengths(len(src), 75)
-    fmm.eval(dev(src), dev(m), dev(tgt), p=8, levels=L, kernel="harmonic")
+    fmm.eval(dev(src), dev(m), dev(tgt), p=8, levels=L, kernel="harmonic", swap=swap)
     top = fmm.topology()
-    T = orc.Tree(src, L, tgt=tgt)
+    T = orc.Tree(src, L, tgt=tgt, swap=swap)
+    if swap and name == "clusters20k":
+        assert len(T.m2p[1]) > 0, "case does not exercise the swapped criterion"
     _compare_topology(orc, top, T, L)
 
 
 # ------------------------------------------------------------------ FMM
 @pytest.mark.parametrize("kernel", ["log", "harmonic"])
-@pytest.mark.parametrize("name,p", [("uniform10k", 17), ("clusters20k", 12), ("gauss10_targets", 20),
-                                    ("lattice_ties", 30), ("spiral_ragged", 9)])
-def test_fmm_matches_oracle_fmm(fmm, orc, name, p, kernel):
+@pytest.mark.parametrize("name,p,swap", [("uniform10k", 17, False), ("clusters20k", 12, False),
+                                         ("gauss10_targets", 20, False), ("lattice_ties", 30, False),
+                                         ("spiral_ragged", 9, False), ("clusters20k", 17, True),
+                                         ("gauss10_targets", 14, True), ("spiral_ragged", 21, True)])
+def test_fmm_matches_oracle_fmm(fmm, orc, name, p, swap, kernel):
     src, tgt, L = _case(name)
     m = workloads.strengths(len(src), 76)
     k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
-    gp, gd = fmm.eval(dev(src), dev(m), dev(tgt), p=p, levels=L, kernel=kernel)
+    gp, gd = fmm.eval(dev(src), dev(m), dev(tgt), p=p, levels=L, kernel=kernel, swap=swap)
     top = fmm.topology(coeffs=True)
-    T = orc.Tree(src, L, tgt=tgt)
+    T = orc.Tree(src, L, tgt=tgt, swap=swap)
     rp, rd, A, B = T.eval(m, p, k, want_coeffs=True)
     # coefficients weighted by their size on the box's disc: a_k / rho^k and
     # b_l rho^l (raw high-order coefficients carry rounding relative to terms
@@ -216,3 +225,24 @@ def test_mixed_close_to_fp64(fmm, orc, name, kernel):
         e_p = nrm(host(gp), rp)
         print("mixed %s %s: phi normwise %.2e" % (name, kernel, e_p))
         assert e_p < 2e-6
+
+
+def test_heavy_boxes_match_oracle(fmm, orc):
+    """A point set with a few large sparse leaves next to dense clusters, so
+    that some boxes exceed the one-wave thresholds of the near field (32
+    entries) and of M2L (256 weak pairs) and take the multi-wave paths."""
+    src = workloads.points("clusters", 200_000, 86)
+    m = workloads.strengths(200_000, 87)
+    L = 6
+    T = orc.Tree(src, L, swap=True)
+    ne = np.diff(T.strong[L][0]) + np.diff(T.m2p[0])
+    nw_max = max(int(np.diff(T.weak[l][0]).max()) for l in range(1, L + 1))
+    assert ne.max() > 32 and nw_max > 256, (ne.max(), nw_max)
+    for kernel, k in (("harmonic", orc.KERNEL_HARMONIC), ("log", orc.KERNEL_LOG)):
+        gp, gd = fmm.eval(dev(src), dev(m), p=12, levels=L, kernel=kernel, swap=True)
+        rp, rd = T.eval(m, 12, k)
+        assert nrm(host(gd), rd) < 1e-12
+        if k == orc.KERNEL_LOG:
+            assert nrm(host(gp), rp) < 1e-12
+        gp2, gd2 = fmm.eval(dev(src), dev(m), p=12, levels=L, kernel=kernel, swap=True, precision="mixed")
+        assert nrm(host(gd2), rd) < 2e-6
