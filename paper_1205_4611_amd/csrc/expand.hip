@@ -309,10 +309,14 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
 
+    // the next chunk's list entry is fetched one iteration ahead
+    int32_t sb_next = (e0 + 8 * w + ps < e1) ? a.widx[e0 + 8 * w + ps] : 0;
     for (int32_t e = e0 + 8 * w; e < e1; e += 8 * nw) {
         const int32_t pe = e + ps;
         const bool valid = pe < e1;
-        int32_t sb = valid ? a.widx[pe] : 0;
+        int32_t sb = valid ? sb_next : 0;
+        const int32_t pn = pe + 8 * nw;
+        sb_next = (pn < e1) ? a.widx[pn] : 0;
         sb = min(max(sb, 0), nbl - 1);
         const int64_t gS = bo + sb;
         const double2 r = make_double2(a.centre[2 * gS] - cT.x, a.centre[2 * gS + 1] - cT.y);
@@ -386,15 +390,19 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
         }
 }
 
-template <int MT, int KS, bool HEAVY>
-__global__ void __launch_bounds__(HEAVY ? 64 * M2L_WAVES : 256) k_m2l64(m2l_args a)
+// One launch: blocks [0, H) take the boxes with more than M2L_HEAVY weak pairs
+// (M2L_WAVES waves per box, fixed-order LDS reduction); the other blocks take
+// the light boxes, one wave per box.
+template <int MT, int KS>
+__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
 {
-    __shared__ double part[HEAVY ? M2L_WAVES : 1][MT * 16][2];
+    __shared__ double part[M2L_WAVES][MT * 16][2];
     const int lane = threadIdx.x & (WAVE - 1);
     const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
     const int P1 = a.p + 1;
-    if (!HEAVY) {
-        const int64_t g = wave_index();
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    if ((int32_t)blockIdx.x >= H) {
+        const int64_t g = (int64_t)(blockIdx.x - H) * M2L_WAVES + w;
         if (g >= a.nb) return;
         int l;
         int32_t e0, e1;
@@ -410,8 +418,7 @@ __global__ void __launch_bounds__(HEAVY ? 64 * M2L_WAVES : 256) k_m2l64(m2l_args
                 if (ps == 0 && row <= a.p) reinterpret_cast<double *>(Bt + row)[comp] = acc[mt][j];
             }
     } else {
-        const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-        for (int64_t g = blockIdx.x; g < a.nb; g += gridDim.x) {
+        for (int64_t g = blockIdx.x; g < a.nb; g += H) {
             int l;
             int32_t e0, e1;
             if (m2l_range(a, g, l, e0, e1) <= M2L_HEAVY) continue;
@@ -482,10 +489,14 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0f;
     acc0 = 0.0;
+    // the next chunk's list entry is fetched one iteration ahead
+    int32_t sb_next = (e0 + 8 * w + ps < e1) ? a.widx[e0 + 8 * w + ps] : 0;
     for (int32_t e = e0 + 8 * w; e < e1; e += 8 * nw) {
         const int32_t pe = e + ps;
         const bool valid = pe < e1;
-        int32_t sb = valid ? a.widx[pe] : 0;
+        int32_t sb = valid ? sb_next : 0;
+        const int32_t pn = pe + 8 * nw;
+        sb_next = (pn < e1) ? a.widx[pn] : 0;
         sb = min(max(sb, 0), nbl - 1);
         const int64_t gS = bo + sb;
         const double2 r = make_double2(a.centre[2 * gS] - cT.x, a.centre[2 * gS + 1] - cT.y);
@@ -574,15 +585,19 @@ __device__ __forceinline__ double m2l32_unscale(double v, int row, double isT)
     return v;
 }
 
-template <int MT, int KS, bool HEAVY>
-__global__ void __launch_bounds__(HEAVY ? 64 * M2L_WAVES : 256) k_m2l32(m2l_args a)
+// One launch: blocks [0, H) take the boxes with more than M2L_HEAVY weak pairs
+// (M2L_WAVES waves per box, fixed-order LDS reduction); the other blocks take
+// the light boxes, one wave per box.
+template <int MT, int KS>
+__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l32(m2l_args a, int32_t H)
 {
-    __shared__ double part[HEAVY ? M2L_WAVES : 1][MT * 16][2];
+    __shared__ double part[M2L_WAVES][MT * 16][2];
     const int lane = threadIdx.x & (WAVE - 1);
     const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
     const int P1 = a.p + 1;
-    if (!HEAVY) {
-        const int64_t g = wave_index();
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    if ((int32_t)blockIdx.x >= H) {
+        const int64_t g = (int64_t)(blockIdx.x - H) * M2L_WAVES + w;
         if (g >= a.nb) return;
         int l;
         int32_t e0, e1;
@@ -602,8 +617,7 @@ __global__ void __launch_bounds__(HEAVY ? 64 * M2L_WAVES : 256) k_m2l32(m2l_args
                 if (ps == 0 && row <= a.p) reinterpret_cast<double *>(Bt + row)[comp] = m2l32_unscale(d, row, isT);
             }
     } else {
-        const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-        for (int64_t g = blockIdx.x; g < a.nb; g += gridDim.x) {
+        for (int64_t g = blockIdx.x; g < a.nb; g += H) {
             int l;
             int32_t e0, e1;
             if (m2l_range(a, g, l, e0, e1) <= M2L_HEAVY) continue;
@@ -722,15 +736,10 @@ hipError_t fmm_l2l(const fmm_eval_args &a, hipStream_t st)
 template <int MT, int KS>
 static void launch_m2l(const m2l_args &m, bool mixed, hipStream_t st)
 {
-    const unsigned nblk = (unsigned)((m.nb + 3) / 4);
-    const unsigned nheavy = (unsigned)(m.nb < 1024 ? m.nb : 1024);
-    if (mixed) {
-        k_m2l32<MT, KS, false><<<nblk, 256, 0, st>>>(m);
-        k_m2l32<MT, KS, true><<<nheavy, 64 * M2L_WAVES, 0, st>>>(m);
-    } else {
-        k_m2l64<MT, KS, false><<<nblk, 256, 0, st>>>(m);
-        k_m2l64<MT, KS, true><<<nheavy, 64 * M2L_WAVES, 0, st>>>(m);
-    }
+    const int32_t H = (int32_t)(m.nb < 512 ? m.nb : 512);
+    const unsigned nblk = (unsigned)(H + (m.nb + M2L_WAVES - 1) / M2L_WAVES);
+    if (mixed) k_m2l32<MT, KS><<<nblk, 64 * M2L_WAVES, 0, st>>>(m, H);
+    else k_m2l64<MT, KS><<<nblk, 64 * M2L_WAVES, 0, st>>>(m, H);
 }
 
 hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st)
