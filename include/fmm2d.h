@@ -59,11 +59,18 @@ extern "C" {
                          sums and radius-scaled coefficients; geometry, theta
                          tests, the top tree levels and the final near+far sum
                          stay FP64 */
+#define FMM2D_MIXED_FAR 2 /* the M2L contraction in FP32 (radius-scaled, as
+                             above); the near field, L2P and everything else
+                             in FP64 */
 
 /* ---- truncation order policy ------------------------------------------ */
 #define FMM2D_P_FIXED 0   /* one order p for every M2L interaction */
-#define FMM2D_P_LEARNED 1 /* per-interaction order predicted by the loaded MLP,
-                             falling back to the fixed p without a model */
+#define FMM2D_P_LEARNED 1 /* per-interaction order predicted by the loaded MLP
+                             (fmm2d_set_porder_model), falling back to the
+                             fixed p without a model or when p is below
+                             FMM2D_PORDER_FEAT_K */
+#define FMM2D_P_GIVEN 2   /* per-interaction orders supplied by the caller
+                             (fmm2d_set_pair_orders) */
 
 /* ---- flags ------------------------------------------------------------ */
 #define FMM2D_FLAG_TIMING 1u        /* record per-phase device times (events) */
@@ -175,7 +182,8 @@ typedef struct fmm2d_topology {
     const int32_t *p2l_idx;
     const double *mpole;   /* [nboxes][p+1] complex multipole coefficients */
     const double *local;   /* [nboxes][p+1] complex local coefficients */
-    const uint8_t *porder; /* [n_weak_total] learned orders, or NULL */
+    const uint8_t *porder; /* [n_weak_total] per-pair M2L orders in weak_idx
+                              order (learned or given), or NULL at fixed p */
 } fmm2d_topology;
 int fmm2d_get_topology(fmm2d_handle *h, fmm2d_topology *out);
 
@@ -194,10 +202,96 @@ typedef struct fmm2d_stats {
     int64_t n_p2l;       /* P2L leaf pairs */
     int64_t n_p2p_pairs; /* point-point pair evaluations in P2P */
     int32_t status;      /* as fmm2d_sync */
-    int32_t used_model;  /* 1 if the learned order was used */
-    int64_t p_hist[65];  /* learned order histogram (p = 0..64) */
+    int32_t used_model;  /* 1 if the learned order model was used */
+    int64_t p_hist[65];  /* M2L pairs per order q = 0..64 (all at p when fixed) */
 } fmm2d_stats;
 int fmm2d_get_stats(fmm2d_handle *h, fmm2d_stats *out);
+
+/* ---- per-interaction truncation order ----------------------------------
+ * The method uses one order p for all M2L interactions (the a-priori rule
+ * p ~ log(TOL)/log(theta) of Sec. 2).  With FMM2D_P_LEARNED or FMM2D_P_GIVEN
+ * each weak pair (T, S) gets its own order q in [1, p]: its M2L reads
+ * a_0..a_q of S and adds to b_0..b_q of T only (eq. (multipole) and
+ * eq. (local) truncated at q).  Storage, P2M, M2M, L2L and L2P stay at p.
+ *
+ * Learned orders come from an MLP on 8 features of the pair (schema 1):
+ *   f0 rho_S/d, f1 rho_T/d, f2 (rho_S+rho_T)/d, f3 l/L,
+ *   f4 log10(|ahat_S|_1 / |ahat_root|_1),
+ *   f5 log10(sum_{k>K/2} |ahat_{S,k}| / |ahat_S|_1),
+ *   f6 log10(|ahat_S|_1 / sum_{S' in weak(T)} |ahat_S'|_1),
+ *   f7 log10(|weak(T)|),
+ * where d = |c_T - c_S|, rho the box radii, l the level, ahat_k = a_k /
+ * sigma^k for k = 0..K (K = FMM2D_PORDER_FEAT_K), sigma = max(rho,
+ * 2^-20 rho_root), log10 arguments floored at 1e-300.
+ * Model layout (FMM2D_PORDER_MODEL_FLOATS floats):
+ *   [W1 32x8 row-major][b1 32][W2 32][b2 1]     trainable (FMM2D_PORDER_NPARAM)
+ *   [mu 8][isd 8]                                  input standardisation
+ *   [lo 8][hi 8]                                   feature range seen in training
+ *   y = W2 . relu(W1 ((f - mu) * isd) + b1) + b2,
+ *   q = clamp(ceil(y + delta), FMM2D_PORDER_QMIN, p); a pair with a feature
+ *   outside [lo, hi] keeps q = p.  All MLP arithmetic is FP32. */
+#define FMM2D_PORDER_SCHEMA 1
+#define FMM2D_PORDER_NFEAT 8
+#define FMM2D_PORDER_HIDDEN 32
+#define FMM2D_PORDER_NPARAM 321
+#define FMM2D_PORDER_MODEL_FLOATS 353
+#define FMM2D_PORDER_FEAT_K 20
+#define FMM2D_PORDER_QMIN 4
+
+/* Load (copy to the device) or, with model == NULL, drop the order model.
+ * model is a HOST array of n_floats == FMM2D_PORDER_MODEL_FLOATS; schema must
+ * be FMM2D_PORDER_SCHEMA; delta is the calibrated offset added to y.
+ * Allocates one small device buffer owned by the handle (this call is not on
+ * the evaluation path).  FMM2D_EINVAL on a wrong size, schema or a non-finite
+ * weight. */
+int fmm2d_set_porder_model(fmm2d_handle *h, const float *model, int64_t n_floats, uint32_t schema, float delta);
+
+/* Orders for FMM2D_P_GIVEN evaluations: orders is a DEVICE uint8 array of n
+ * entries in weak_idx order (as exported by fmm2d_get_topology); values are
+ * clamped to [1, p].  The caller keeps it alive while such evaluations run;
+ * NULL clears it.  An evaluation with more weak pairs than n uses p for the
+ * rest and fmm2d_sync reports FMM2D_EINVAL. */
+int fmm2d_set_pair_orders(fmm2d_handle *h, const uint8_t *orders, int64_t n);
+
+/* Features of every weak pair of the last evaluation (which must have used
+ * p >= FMM2D_PORDER_FEAT_K), in weak_idx order: feat is a DEVICE float array
+ * [n_cap][8]; pairs beyond n_cap are skipped.  Asynchronous on stream (the
+ * evaluation's stream). */
+int fmm2d_pair_features(fmm2d_handle *h, float *feat, int64_t n_cap, void *stream);
+
+/* Training labels from the last evaluation, which must have used one fixed
+ * order P <= 63 (a high order, e.g. 40).  For weak pair (T, S) with rho =
+ * c_T - c_S, the truncation error bound at order q is
+ *   e_q = sum_{l=0..P} |b_l^(q) - b_l^(P)| rho_T^l,
+ * b^(q) the M2L of S truncated at q (as above), and the label is the smallest
+ * q in [qmin, qmax] with e_q <= tol * min_{y in T} |val(y)| / max(|weak(T)|, 1),
+ * else qmax.  val is a DEVICE array [2*n_tgt] in the caller's target order of
+ * the function the expansions represent (Phi for FMM2D_KERNEL_LOG, Phi' for
+ * FMM2D_KERNEL_HARMONIC), usually the output of that evaluation.  labels is a
+ * DEVICE uint8 array of n_cap entries, weak_idx order.  Asynchronous.
+ * FMM2D_EINVAL if the last evaluation used per-pair orders or P > 63, or
+ * unless 0 <= qmin <= qmax <= P. */
+int fmm2d_pair_labels(fmm2d_handle *h, const double *val, double tol, int32_t qmin, int32_t qmax,
+                      uint8_t *labels, int64_t n_cap, void *stream);
+
+/* MLP training kernels (FP32, DEVICE pointers, asynchronous on stream).
+ *   forward: y[i] = MLP(x[i]) for x [n][8] raw features (the model's
+ *            standardisation is applied), model as above.
+ *   grad:    gradient of the pinball loss (1/n) sum_i rho_tau(q_i - y_i),
+ *            rho_tau(u) = u (tau - [u < 0]), with respect to the
+ *            FMM2D_PORDER_NPARAM trainable parameters -> grad [321]; the loss
+ *            -> *loss (device, may be NULL).  work is a device buffer of
+ *            fmm2d_mlp_work_size(n) bytes.  The sum runs in a fixed order
+ *            (deterministic).
+ *   adam:    one bias-corrected Adam step (step >= 1) on the trainable
+ *            parameters of model, with moment buffers m, v [321] (zeroed by
+ *            the caller before step 1). */
+size_t fmm2d_mlp_work_size(int64_t n);
+int fmm2d_mlp_forward(fmm2d_handle *h, const float *model, const float *x, int64_t n, float *y, void *stream);
+int fmm2d_mlp_grad(fmm2d_handle *h, const float *model, const float *x, const float *q, int64_t n, float tau,
+                   float *grad, float *loss, void *work, size_t work_bytes, void *stream);
+int fmm2d_mlp_adam(fmm2d_handle *h, float *model, const float *grad, float *m, float *v, int32_t step, float lr,
+                   float beta1, float beta2, float eps, void *stream);
 
 #ifdef __cplusplus
 }

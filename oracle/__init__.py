@@ -94,6 +94,12 @@ def _configure(lib):
     lib.orc_eval.restype = i32
     lib.orc_direct_branch.argtypes = [P, P, P, i64, P]
     lib.orc_direct_branch.restype = i32
+    lib.orc_eval_orders.argtypes = [P, P, i32, i32, P, P, P, P, P]
+    lib.orc_eval_orders.restype = i32
+    lib.orc_labels.argtypes = [P, P, i32, P, f64, i32, i32, P, P, P]
+    lib.orc_labels.restype = i32
+    lib.orc_pair_err.argtypes = [i32, P, f64, f64, f64, i32, i32, P]
+    lib.orc_pair_err.restype = None
     return lib
 
 
@@ -208,6 +214,15 @@ def p2l(kernel, p, c, x, m, out=None):
     return o.view(np.complex128)
 
 
+def pair_err(P, a, rho, rT, qmin, qmax):
+    """e_q (q = qmin..qmax) of one M2L pair: multipole a (order P) about c_S,
+    rho = c_T - c_S, target radius rT (see orc_pair_err)."""
+    aa = _c(a, np.float64)
+    e = np.zeros(qmax - qmin + 1)
+    _load().orc_pair_err(int(P), _p(aa), rho.real, rho.imag, float(rT), int(qmin), int(qmax), _p(e))
+    return e
+
+
 def l2l(p, b_par, r, out=None):
     """Re-centre a local expansion from c_p to c_c, r = c_c - c_p (exact)."""
     b = _c(b_par, np.float64)
@@ -305,9 +320,30 @@ class Tree:
     def boxes(self, l):
         return slice(box_offset(l), box_offset(l + 1))
 
-    def eval(self, m, p, kernel=KERNEL_LOG, want_coeffs=False):
+    def n_weak(self):
+        return sum(int(off[-1]) for off, _ in self.weak)
+
+    def weak_pairs(self):
+        """(level, target box, source box) of every weak pair, per-level box
+        numbers, in the concatenated order of levels 1..L (the order of
+        per-pair orders and labels)."""
+        lv, tb, sb = [], [], []
+        for l in range(1, self.L + 1):
+            off, idx = self.weak[l]
+            cnt = np.diff(off)
+            lv.append(np.full(idx.size, l, np.int64))
+            tb.append(np.repeat(np.arange(4 ** l, dtype=np.int64), cnt))
+            sb.append(idx.astype(np.int64))
+        if not lv:
+            z = np.zeros(0, np.int64)
+            return z, z, z
+        return np.concatenate(lv), np.concatenate(tb), np.concatenate(sb)
+
+    def eval(self, m, p, kernel=KERNEL_LOG, want_coeffs=False, orders=None):
         """Whole FMM evaluation (Sec. 2).  Returns (phi, dphi[, A, B]) in the
-        original target order; A, B are [nboxes, p+1] complex."""
+        original target order; A, B are [nboxes, p+1] complex.  orders
+        (optional, uint8 [n_weak], weak_pairs() order) truncates each M2L
+        pair at its own order."""
         lib = self._lib
         mm = _c(m, np.float64)
         nt = self.nt or self.ns
@@ -316,13 +352,36 @@ class Tree:
         nb = box_offset(self.L + 1)
         A = np.zeros(2 * nb * (p + 1)) if want_coeffs else None
         B = np.zeros(2 * nb * (p + 1)) if want_coeffs else None
-        rc = lib.orc_eval(self._h, _p(mm), kernel, p, _p(phi), _p(dphi), _p(A), _p(B))
+        if orders is not None:
+            q = np.ascontiguousarray(orders, dtype=np.uint8)
+            if q.size != self.n_weak():
+                raise ValueError("orders must have one entry per weak pair (%d)" % self.n_weak())
+            rc = lib.orc_eval_orders(self._h, _p(mm), kernel, p, _p(q), _p(phi), _p(dphi), _p(A), _p(B))
+        else:
+            rc = lib.orc_eval(self._h, _p(mm), kernel, p, _p(phi), _p(dphi), _p(A), _p(B))
         if rc != 0:
             raise ValueError("oracle eval failed")
         out = [phi.view(np.complex128) if kernel == KERNEL_LOG else None, dphi.view(np.complex128)]
         if want_coeffs:
             out += [A.view(np.complex128).reshape(nb, p + 1), B.view(np.complex128).reshape(nb, p + 1)]
         return tuple(out)
+
+    def labels(self, A, P, val, tol, qmin=4, qmax=30):
+        """Per-pair labels from multipoles A [nboxes, P+1] of an evaluation
+        at order P and the values val (original target order): returns
+        (label uint8, e_q [n_weak, qmax-qmin+1], budget) in weak_pairs()
+        order (see orc_labels)."""
+        nw = self.n_weak()
+        a = np.ascontiguousarray(A, dtype=np.complex128).view(np.float64)
+        v = np.ascontiguousarray(val, dtype=np.complex128).view(np.float64)
+        lab = np.zeros(max(nw, 1), np.uint8)
+        err = np.zeros(max(nw, 1) * (qmax - qmin + 1))
+        bud = np.zeros(max(nw, 1))
+        rc = self._lib.orc_labels(self._h, _p(a), int(P), _p(v), float(tol), int(qmin), int(qmax),
+                                  _p(lab), _p(err), _p(bud))
+        if rc != 0:
+            raise ValueError("oracle labels: bad arguments")
+        return lab[:nw], err.reshape(-1, qmax - qmin + 1)[:nw], bud[:nw]
 
     def direct_branch(self, m, tsel):
         """Direct sum of Phi on the branch the FMM far field follows (see the

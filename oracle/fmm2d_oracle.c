@@ -23,6 +23,10 @@
  *                      L2P and P2P (Sec. 2)
  *   orc_direct_branch  direct sum on the branch of log that the FMM far field
  *                      follows (reading of the log term of eq. (multipole))
+ *   orc_eval_orders    orc_eval with one truncation order per M2L pair
+ *   orc_pair_err       truncation error bound e_q of one M2L pair at order q
+ *   orc_labels         the smallest order whose e_q meets a per-box budget
+ *                      (training labels for the learned order)
  */
 #include <complex.h>
 #include <math.h>
@@ -581,8 +585,26 @@ void orc_get_tree(const orc_tree *T, int32_t *perm, int32_t *tperm, int64_t *sst
  * leaf L2P plus P2P over its strong list.  A and B (optional outputs) receive
  * the multipole and local coefficients of every box, [nboxes][p+1] complex,
  * with B holding the complete local expansion (M2L plus inherited L2L). */
+/* qw (optional): one order q in [1, p] per weak pair, in the order of the
+ * weak lists of levels 1, 2, ..., L concatenated; pair (T, S) then adds
+ * orc_m2l at order q (a_0..a_q of S into b_0..b_q of T). */
+static int eval_impl(const orc_tree *T, const double *m, int kernel, int p, const unsigned char *qw,
+                     double *phi, double *dphi, double *A_out, double *B_out);
+
 int orc_eval(const orc_tree *T, const double *m, int kernel, int p,
              double *phi, double *dphi, double *A_out, double *B_out)
+{
+    return eval_impl(T, m, kernel, p, NULL, phi, dphi, A_out, B_out);
+}
+
+int orc_eval_orders(const orc_tree *T, const double *m, int kernel, int p, const unsigned char *qw,
+                    double *phi, double *dphi, double *A_out, double *B_out)
+{
+    return eval_impl(T, m, kernel, p, qw, phi, dphi, A_out, B_out);
+}
+
+static int eval_impl(const orc_tree *T, const double *m, int kernel, int p, const unsigned char *qw,
+                     double *phi, double *dphi, double *A_out, double *B_out)
 {
     if (p < 1 || p >= ORC_BMAX / 2) return -1;
     binom_init();
@@ -623,17 +645,26 @@ int orc_eval(const orc_tree *T, const double *m, int kernel, int p,
             }
         }
     }
-    /* M2L over every weak pair, then L2L downward */
+    /* M2L over every weak pair (at its own order if qw is given), then L2L
+     * downward */
+    int64_t qbase = 0;
     for (int l = 1; l <= L; ++l) {
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t b = 0; b < nbox(l); ++b) {
             int64_t g = box_off(l) + b;
             for (int64_t e = T->woff[l][b]; e < T->woff[l][b + 1]; ++e) {
                 int64_t s = box_off(l) + T->widx[l][e];
-                orc_m2l(p, A + 2 * P1 * s, T->cen[2 * g] - T->cen[2 * s],
+                int q = p;
+                if (qw) {
+                    q = qw[qbase + e];
+                    if (q < 1) q = 1;
+                    if (q > p) q = p;
+                }
+                orc_m2l(q, A + 2 * P1 * s, T->cen[2 * g] - T->cen[2 * s],
                         T->cen[2 * g + 1] - T->cen[2 * s + 1], B + 2 * P1 * g);
             }
         }
+        qbase += T->woff[l][nbox(l)];
     }
     for (int l = 1; l <= L; ++l) {
 #pragma omp parallel for schedule(static)
@@ -802,4 +833,77 @@ int orc_direct_branch(const orc_tree *T, const double *m, const int64_t *tsel,
     }
     free(leaf_of);
     return bad ? -bad : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Truncation error bound of one M2L pair.  a: multipole at order P about c_S,
+ * rho = c_T - c_S, rT the target radius.  b^(q) = orc_m2l at order q (a_0..a_q
+ * into b_0..b_q, zero above), and
+ *     e_q = sum_{l=0..P} |b_l^(q) - b_l^(P)| rT^l,
+ * which bounds the error of the pair truncated at q (against order P) over
+ * the disc |z - c_T| <= rT.  Writes e_q for q = qmin..qmax into e[]. */
+void orc_pair_err(int P, const double *a, double rhox, double rhoy, double rT, int qmin, int qmax, double *e)
+{
+    double *bP = (double *)calloc((size_t)(2 * (P + 1)), sizeof(double));
+    double *bq = (double *)calloc((size_t)(2 * (P + 1)), sizeof(double));
+    orc_m2l(P, a, rhox, rhoy, bP);
+    for (int q = qmin; q <= qmax; ++q) {
+        memset(bq, 0, (size_t)(2 * (P + 1)) * sizeof(double));
+        orc_m2l(q, a, rhox, rhoy, bq); /* q = 0: the log term of b_0 only */
+        double eq = 0.0, rl = 1.0;
+        for (int l = 0; l <= P; ++l) {
+            eq += cabs((bq[2 * l] - bP[2 * l]) + I * (bq[2 * l + 1] - bP[2 * l + 1])) * rl;
+            rl *= rT;
+        }
+        e[q - qmin] = eq;
+    }
+    free(bP); free(bq);
+}
+
+/* Training labels for a per-pair truncation order.  A holds the multipoles of
+ * an evaluation at order P.  With V(T) = min over the targets y in box T of
+ * |val(y)| (val in the original target order), the budget of T is
+ * tol V(T) / max(|weak(T)|, 1), and the label of weak pair (T, S) is the
+ * smallest q in [qmin, qmax] whose orc_pair_err e_q is <= that budget, else
+ * qmax.  Outputs, per weak pair in the concatenated order of levels 1..L:
+ * label[], and optionally err[pair][qmax - qmin + 1] and budget_out[pair]. */
+int orc_labels(const orc_tree *T, const double *A, int P, const double *val, double tol, int qmin,
+               int qmax, unsigned char *label, double *err, double *budget_out)
+{
+    if (P < 1 || P >= ORC_BMAX / 2 || qmin < 0 || qmax < qmin || qmax > P) return -1;
+    binom_init();
+    int L = T->L;
+    int64_t P1 = P + 1, nq = qmax - qmin + 1;
+    const int32_t *tperm = T->nt ? T->tperm : T->perm;
+    const int64_t *tst = T->nt ? T->tstart : T->sstart;
+    int64_t qbase = 0;
+    for (int l = 1; l <= L; ++l) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t b = 0; b < nbox(l); ++b) {
+            int64_t g = box_off(l) + b;
+            double vmin = INFINITY;
+            for (int64_t k = tst[start_off(l) + b]; k < tst[start_off(l) + b + 1]; ++k) {
+                int32_t i = tperm[k];
+                double v = cabs(val[2 * i] + I * val[2 * i + 1]);
+                if (v < vmin) vmin = v;
+            }
+            int64_t nw = T->woff[l][b + 1] - T->woff[l][b];
+            double bud = tol * vmin / (double)(nw > 0 ? nw : 1);
+            double *eq = (double *)malloc((size_t)nq * sizeof(double));
+            for (int64_t e = T->woff[l][b]; e < T->woff[l][b + 1]; ++e) {
+                int64_t s = box_off(l) + T->widx[l][e];
+                orc_pair_err(P, A + 2 * P1 * s, T->cen[2 * g] - T->cen[2 * s], T->cen[2 * g + 1] - T->cen[2 * s + 1],
+                             T->rad[g], qmin, qmax, eq);
+                int lab = qmax;
+                for (int q = qmax; q >= qmin; --q)
+                    if (eq[q - qmin] <= bud) lab = q;
+                label[qbase + e] = (unsigned char)lab;
+                if (err) memcpy(err + (qbase + e) * nq, eq, (size_t)nq * sizeof(double));
+                if (budget_out) budget_out[qbase + e] = bud;
+            }
+            free(eq);
+        }
+        qbase += T->woff[l][nbox(l)];
+    }
+    return 0;
 }

@@ -13,6 +13,11 @@
 
 // status bits written by kernels into the handle's device status word
 #define FMM_ST_LIST_OVERFLOW 1
+#define FMM_ST_ORDERS_SHORT 2   // caller's pair orders shorter than the weak list
+
+// learned truncation order
+#define FMM_NF FMM2D_PORDER_NFEAT
+#define FMM_HID FMM2D_PORDER_HIDDEN
 
 static inline int64_t box_off(int l) { return ((((int64_t)1) << (2 * l)) - 1) / 3; }
 static inline int64_t nbox(int l) { return ((int64_t)1) << (2 * l); }
@@ -46,12 +51,11 @@ struct fmm_layout {
     // offsets (bytes)
     size_t keys[2], vals[2];     // radix sort ping-pong (max(ns,nt) each)
     size_t hist;                 // radix histogram / scan block sums
-    size_t sl[1];                // source lists: 6 x ns int32 (lx, ly, li + partition outputs)
-    size_t tl[1];                // target lists: 6 x nt int32
-    size_t sside, tside;         // side flag per original index
-    size_t bsum;                 // partition block sums (6 lists)
+    size_t srec, trec;           // 4 x n records (x- and y-ordered lists, ping-pong)
+    size_t perm, tperm;          // leaf-order original indices (sources / targets)
+    size_t bsum;                 // partition / scan block sums
     size_t sstep, tstep;         // per-step starts (sources / targets)
-    size_t seg_axis, seg_nlo, seg_tlo, seg_LO, seg_TLO;
+    size_t seg_axis, seg_pc, seg_pi, seg_nlo, seg_tlo, seg_LO, seg_TLO;
     size_t sstart, tstart;       // per-level starts (output)
     size_t centre, radius;
     size_t wcnt, scnt;           // per-box list counts (current level)
@@ -65,8 +69,10 @@ struct fmm_layout {
     size_t m32;                  // float2 strengths in leaf order (mixed)
     size_t A, B;                 // FP64 multipoles / locals [nb][p+1] complex
     size_t A32;                  // FP32 radius-scaled multipoles (mixed)
-    size_t feat, porder, pbucket;// learned order: features, orders, bucketed pairs
-    size_t pairs;                // M2L pair table (target, source) for bucketing
+    size_t n1, tail;             // per-box coefficient norms (order features)
+    size_t vmin, budget;         // per-box label budget
+    size_t qw;                   // uint8 order per weak pair, weak-list order
+    size_t sw, sp;               // weak pairs sorted by order within a box: source, order
     size_t total;
 };
 
@@ -93,7 +99,7 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
 hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st);
 
 struct fmm_eval_args {
-    int L, p, kernel, mixed;
+    int L, p, kernel, mixed;      // mixed: 0 FP64, 1 FP32 near and far field, 2 FP32 far field only
     int64_t ns, nt;               // nt == ns when at sources
     int at_sources;
     const char *ws;
@@ -101,6 +107,7 @@ struct fmm_eval_args {
     const double *binom;          // [FMM_BN][FMM_BN] FP64
     int32_t cap;
     int swap;
+    int porder;                   // per-pair orders (sorted lists sw/sp) in use
 };
 hipError_t fmm_p2m(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_m2m(const fmm_eval_args &a, hipStream_t st);
@@ -108,6 +115,36 @@ hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_l2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_p2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_p2p_l2p(const fmm_eval_args &a, double *phi, double *dphi, hipStream_t st);
+
+// learned / given per-pair orders (porder.hip)
+struct fmm_porder_args {
+    const double *centre, *radius, *n1, *tail;
+    const int32_t *woff, *widx;
+    const float *model;           // device model or NULL
+    float delta;
+    const uint8_t *given;         // caller's orders or NULL
+    int64_t ngiven;
+    int p, L;
+    int64_t nb;
+    int32_t cap;
+    uint8_t *qw;
+    int32_t *sw;
+    uint8_t *sp;
+    int32_t *status;
+};
+hipError_t fmm_box_norms(const double2 *A, const double *radius, int p, int64_t nb, double *n1, double *tail,
+                         hipStream_t st);
+hipError_t fmm_features(const fmm_porder_args &a, int64_t nfeat_cap, float *feat, hipStream_t st);
+hipError_t fmm_porder(const fmm_porder_args &a, hipStream_t st);
+hipError_t fmm_labels(const fmm_porder_args &a, const double2 *A, const double *binom, const int32_t *tperm,
+                      const int32_t *tstart, const double *val, double tol, int P, int kernel, int qmin, int qmax,
+                      int64_t nlab_cap, double *vmin, double *budget, uint8_t *label, hipStream_t st);
+int64_t fmm_mlp_grad_blocks(int64_t n);
+hipError_t fmm_mlp_forward(const float *w, const float *x, int64_t n, float *y, hipStream_t st);
+hipError_t fmm_mlp_grad(const float *w, const float *x, const float *q, int64_t n, float tau, float *part,
+                        float *grad, float *loss, hipStream_t st);
+hipError_t fmm_mlp_adam(float *w, const float *grad, float *m, float *v, int step, float lr, float b1, float b2,
+                        float eps, hipStream_t st);
 
 hipError_t fmm_direct(int64_t ns, const double *src, const double *m, int64_t nt,
                       const double *tgt, const int64_t *tsel, int64_t nsel, int kernel,

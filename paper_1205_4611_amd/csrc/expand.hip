@@ -248,6 +248,8 @@ struct m2l_args {
     double2 *B;             // output, written (not accumulated)
     const int32_t *woff;    // per-level offsets
     const int32_t *widx;    // global weak list
+    const int32_t *sw;      // per-pair orders: sources sorted by order within a box, or NULL
+    const uint8_t *sp;      //   and their orders (ascending within a box)
     const double *binom;
     int64_t nb;
     int L, p, kernel;
@@ -309,15 +311,25 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
 
+    const int32_t *wl = a.sw ? a.sw : a.widx;
     // the next chunk's list entry is fetched one iteration ahead
-    int32_t sb_next = (e0 + 8 * w + ps < e1) ? a.widx[e0 + 8 * w + ps] : 0;
+    int32_t sb_next = (e0 + 8 * w + ps < e1) ? wl[e0 + 8 * w + ps] : 0;
     for (int32_t e = e0 + 8 * w; e < e1; e += 8 * nw) {
         const int32_t pe = e + ps;
         const bool valid = pe < e1;
         int32_t sb = valid ? sb_next : 0;
         const int32_t pn = pe + 8 * nw;
-        sb_next = (pn < e1) ? a.widx[pn] : 0;
+        sb_next = (pn < e1) ? wl[pn] : 0;
         sb = min(max(sb, 0), nbl - 1);
+        // order of this lane's pair (q) and the largest order of the chunk
+        // (qc, its last pair: orders ascend within a box), which bounds the
+        // k-steps and row tiles the chunk needs
+        int q = p, qc = p;
+        if (a.sp) {
+            q = valid ? (int)a.sp[pe] : 0;
+            qc = __builtin_amdgcn_readfirstlane((int)a.sp[min(e + 7, e1 - 1)]);
+        }
+        const int ksn = (qc + 3) >> 2, mtn = (qc >> 4) + 1;
         const int64_t gS = bo + sb;
         const double2 r = make_double2(a.centre[2 * gS] - cT.x, a.centre[2 * gS + 1] - cT.y);
         const double2 rinv = valid ? cinv(r) : make_double2(0.0, 0.0);
@@ -326,16 +338,19 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
         const double2 r2 = cmul(rinv, rinv);
         const double2 r4 = cmul(r2, r2);
         double2 pw = rinv;
-        for (int q = 0; q < kq; ++q) pw = cmul(pw, rinv);
+        for (int t = 0; t < kq; ++t) pw = cmul(pw, rinv);
         double bop[KS];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int kk = 4 * ks + kq + 1;
-            const double2 ak = (valid && kk <= p) ? As[kk] : make_double2(0.0, 0.0);
-            double2 v = cmul(ak, pw);
-            if (kk & 1) { v.x = -v.x; v.y = -v.y; }
-            bop[ks] = comp ? v.y : v.x;
-            pw = cmul(pw, r4);
+            bop[ks] = 0.0;
+            if (ks < ksn) {
+                const double2 ak = (valid && kk <= q) ? As[kk] : make_double2(0.0, 0.0);
+                double2 v = cmul(ak, pw);
+                if (kk & 1) { v.x = -v.x; v.y = -v.y; }
+                bop[ks] = comp ? v.y : v.x;
+                pw = cmul(pw, r4);
+            }
         }
         dbl4 C[MT];
 #pragma unroll
@@ -344,14 +359,16 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                C[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
+                if (ks < ksn && mt < mtn)
+                    C[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
         // post-scale: row l = 16 mt + 4 j + kq gets r^{-l} (B_l - a_0/l)
         const double2 a0 = (valid && LOG) ? As[0] : make_double2(0.0, 0.0);
         const double2 r16 = cmul(cmul(r4, r4), cmul(r4, r4));
         double2 base = make_double2(1.0, 0.0);
-        for (int q = 0; q < kq; ++q) base = cmul(base, rinv);
+        for (int t = 0; t < kq; ++t) base = cmul(base, rinv);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
+            if (mt >= mtn) break;
             double2 pr = base;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -364,7 +381,7 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
                     Bl.y -= a0.y / row;
                 }
                 const double2 res = cmul(Bl, pr);
-                if (valid && row <= p) acc[mt][j] += comp ? res.y : res.x;
+                if (valid && row <= q) acc[mt][j] += comp ? res.y : res.x;
                 pr = cmul(pr, r4);
             }
             base = cmul(base, r16);
@@ -489,15 +506,22 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0f;
     acc0 = 0.0;
+    const int32_t *wl = a.sw ? a.sw : a.widx;
     // the next chunk's list entry is fetched one iteration ahead
-    int32_t sb_next = (e0 + 8 * w + ps < e1) ? a.widx[e0 + 8 * w + ps] : 0;
+    int32_t sb_next = (e0 + 8 * w + ps < e1) ? wl[e0 + 8 * w + ps] : 0;
     for (int32_t e = e0 + 8 * w; e < e1; e += 8 * nw) {
         const int32_t pe = e + ps;
         const bool valid = pe < e1;
         int32_t sb = valid ? sb_next : 0;
         const int32_t pn = pe + 8 * nw;
-        sb_next = (pn < e1) ? a.widx[pn] : 0;
+        sb_next = (pn < e1) ? wl[pn] : 0;
         sb = min(max(sb, 0), nbl - 1);
+        int q = p, qc = p; // as in the FP64 kernel
+        if (a.sp) {
+            q = valid ? (int)a.sp[pe] : 0;
+            qc = __builtin_amdgcn_readfirstlane((int)a.sp[min(e + 7, e1 - 1)]);
+        }
+        const int ksn = (qc + 3) >> 2, mtn = (qc >> 4) + 1;
         const int64_t gS = bo + sb;
         const double2 r = make_double2(a.centre[2 * gS] - cT.x, a.centre[2 * gS + 1] - cT.y);
         const double sS = scale_radius(a.radius[gS], rmin);
@@ -512,16 +536,19 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
         const float2 *As = a.A32 + gS * P1;
         const float2 u2 = cmulf(u, u), u4 = cmulf(u2, u2);
         float2 pw = u;
-        for (int q = 0; q < kq; ++q) pw = cmulf(pw, u);
+        for (int t = 0; t < kq; ++t) pw = cmulf(pw, u);
         float bop[KS];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int kk = 4 * ks + kq + 1;
-            const float2 ak = (valid && kk <= p) ? As[kk] : make_float2(0.0f, 0.0f);
-            float2 t = cmulf(ak, pw);
-            if (kk & 1) { t.x = -t.x; t.y = -t.y; }
-            bop[ks] = comp ? t.y : t.x;
-            pw = cmulf(pw, u4);
+            bop[ks] = 0.0f;
+            if (ks < ksn) {
+                const float2 ak = (valid && kk <= q) ? As[kk] : make_float2(0.0f, 0.0f);
+                float2 t = cmulf(ak, pw);
+                if (kk & 1) { t.x = -t.x; t.y = -t.y; }
+                bop[ks] = comp ? t.y : t.x;
+                pw = cmulf(pw, u4);
+            }
         }
         flt4 C[MT];
 #pragma unroll
@@ -530,15 +557,17 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                C[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
+                if (ks < ksn && mt < mtn)
+                    C[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
         const double2 a064 = (valid && LOG) ? a.A[gS * P1] : make_double2(0.0, 0.0);
         const float2 a0 = make_float2((float)a064.x, (float)a064.y);
         const float2 v2 = cmulf(v, v), v4 = cmulf(v2, v2);
         const float2 v16 = cmulf(cmulf(v4, v4), cmulf(v4, v4));
         float2 base = make_float2(1.0f, 0.0f);
-        for (int q = 0; q < kq; ++q) base = cmulf(base, v4);
+        for (int t = 0; t < kq; ++t) base = cmulf(base, v4);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
+            if (mt >= mtn) break;
             float2 pr = base;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -551,7 +580,7 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
                     Bl.y -= a0.y / row;
                 }
                 const float2 res = cmulf(Bl, pr);
-                if (valid && row <= p) acc[mt][j] += comp ? res.y : res.x;
+                if (valid && row <= q) acc[mt][j] += comp ? res.y : res.x;
                 pr = cmulf(pr, v);
             }
             base = cmulf(base, v16);
@@ -753,6 +782,8 @@ hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st)
     m.B = WSC(double2, lay.B);
     m.woff = WSC(int32_t, lay.woff);
     m.widx = WSC(int32_t, lay.widx);
+    m.sw = a.porder ? WSC(int32_t, lay.sw) : nullptr;
+    m.sp = a.porder ? WSC(uint8_t, lay.sp) : nullptr;
     m.binom = a.binom;
     m.nb = lay.nb;
     m.L = a.L;

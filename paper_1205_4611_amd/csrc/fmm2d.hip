@@ -16,12 +16,17 @@ struct fmm2d_handle {
     hipEvent_t ev[FMM2D_NPHASE + 1];
     int timing_valid;
     hipStream_t last_stream;
+    // learned order model (device copy, owned) and caller-given orders (not owned)
+    float *d_model;
+    float delta;
+    const uint8_t *given;
+    int64_t ngiven;
     // last evaluation
     int have_topo;
     fmm_layout lay;
     const char *ws;
     int64_t ns, nt;
-    int L, p, at_sources, used_model;
+    int L, p, kernel, at_sources, used_orders, used_model;
 };
 
 static int fail(fmm2d_handle *h, int code, const char *fmt, ...)
@@ -99,16 +104,18 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->hist = take(4 * (hist_n > seg_scan_n ? hist_n : seg_scan_n));
     {
         int64_t a = fmm_scan_blocks(hist_n) + 1;
-        int64_t b = 6 * (fmm_scan_blocks(nmax) + 1);
+        int64_t b = 4 * (fmm_scan_blocks(nmax) + 1);
         lay->bsum = take(4 * (a > b ? a : b));
     }
-    lay->sl[0] = take(4 * 6 * ns);
-    lay->tl[0] = take(4 * 6 * nt);
-    lay->sside = take(ns);
-    lay->tside = take(nt);
+    lay->srec = take(24 * 4 * ns);
+    lay->trec = take(24 * 4 * nt);
+    lay->perm = take(4 * ns);
+    lay->tperm = take(4 * nt);
     lay->sstep = take(4 * lay->nstep);
     lay->tstep = take(4 * lay->nstep);
     lay->seg_axis = take(lay->nleaf + 1);
+    lay->seg_pc = take(8 * (lay->nleaf + 1));
+    lay->seg_pi = take(4 * (lay->nleaf + 1));
     lay->seg_nlo = take(4 * (lay->nleaf + 1));
     lay->seg_tlo = take(4 * (lay->nleaf + 1));
     lay->seg_LO = take(4 * (lay->nleaf + 2));
@@ -133,10 +140,17 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->lbsum = take(4 * (fmm_scan_blocks(lay->nleaf) + 2));
     lay->srcs = take(32 * ns);
     lay->tgts = take(16 * nt);
-    lay->m32 = mixed ? take(8 * ns) : 0;
+    lay->m32 = mixed == 1 ? take(8 * ns) : 0;
     lay->A = take(16 * lay->nb * P1);
     lay->B = take(16 * lay->nb * P1);
     lay->A32 = mixed ? take(8 * lay->nb * P1) : 0;
+    lay->n1 = take(8 * lay->nb);
+    lay->tail = take(8 * lay->nb);
+    lay->vmin = take(8 * lay->nb);
+    lay->budget = take(8 * lay->nb);
+    lay->qw = learned ? take(lay->listcap) : 0;
+    lay->sw = learned ? take(4 * lay->listcap) : 0;
+    lay->sp = learned ? take(lay->listcap) : 0;
     lay->total = o;
     return 0;
 }
@@ -187,6 +201,7 @@ extern "C" void fmm2d_destroy(fmm2d_handle *h)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->d_status) (void)hipFree(h->d_status);
     if (h->d_binom) (void)hipFree(h->d_binom);
+    if (h->d_model) (void)hipFree(h->d_model);
     (void)hipSetDevice(prev);
     free(h);
 }
@@ -201,9 +216,9 @@ static int resolve(fmm2d_handle *h, int64_t ns, const fmm2d_opts *o, int *L, int
     if (!(o->theta > 0.0 && o->theta < 1.0)) return fail(h, FMM2D_EINVAL, "theta must be in (0,1)");
     if (o->kernel != FMM2D_KERNEL_LOG && o->kernel != FMM2D_KERNEL_HARMONIC)
         return fail(h, FMM2D_EINVAL, "unknown kernel %u", o->kernel);
-    if (o->precision != FMM2D_FP64 && o->precision != FMM2D_MIXED)
+    if (o->precision != FMM2D_FP64 && o->precision != FMM2D_MIXED && o->precision != FMM2D_MIXED_FAR)
         return fail(h, FMM2D_EINVAL, "unknown precision %u", o->precision);
-    if (o->porder != FMM2D_P_FIXED && o->porder != FMM2D_P_LEARNED)
+    if (o->porder != FMM2D_P_FIXED && o->porder != FMM2D_P_LEARNED && o->porder != FMM2D_P_GIVEN)
         return fail(h, FMM2D_EINVAL, "unknown order policy %u", o->porder);
     int pp = o->p;
     if (pp == 0) {
@@ -234,13 +249,34 @@ extern "C" int fmm2d_workspace_size(fmm2d_handle *h, int64_t n_src, int64_t n_tg
     if (rc) return rc;
     if (n_tgt < 0 || n_tgt > ((int64_t)1 << 30)) return fail(h, FMM2D_EINVAL, "n_tgt out of range");
     fmm_layout lay;
-    fmm_plan_layout(n_src, n_tgt, L, p, cap, opts->precision == FMM2D_MIXED, opts->porder == FMM2D_P_LEARNED,
-                    &lay);
+    fmm_plan_layout(n_src, n_tgt, L, p, cap, (int)opts->precision, opts->porder != FMM2D_P_FIXED, &lay);
     *bytes = lay.total;
     return FMM2D_OK;
 }
 
 __global__ void k_zero_status(int32_t *s) { s[threadIdx.x] = 0; }
+
+static fmm_porder_args porder_args(fmm2d_handle *h, char *w, const fmm_layout &lay, int L, int p, int cap)
+{
+    fmm_porder_args a;
+    memset(&a, 0, sizeof(a));
+    a.centre = reinterpret_cast<const double *>(w + lay.centre);
+    a.radius = reinterpret_cast<const double *>(w + lay.radius);
+    a.n1 = reinterpret_cast<const double *>(w + lay.n1);
+    a.tail = reinterpret_cast<const double *>(w + lay.tail);
+    a.woff = reinterpret_cast<const int32_t *>(w + lay.woff);
+    a.widx = reinterpret_cast<const int32_t *>(w + lay.widx);
+    a.p = p;
+    a.L = L;
+    a.nb = lay.nb;
+    a.cap = (int32_t)lay.listcap;
+    (void)cap;
+    a.qw = lay.qw ? reinterpret_cast<uint8_t *>(w + lay.qw) : nullptr;
+    a.sw = lay.sw ? reinterpret_cast<int32_t *>(w + lay.sw) : nullptr;
+    a.sp = lay.sp ? reinterpret_cast<uint8_t *>(w + lay.sp) : nullptr;
+    a.status = h->d_status;
+    return a;
+}
 
 extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, const double *m, int64_t n_tgt,
                           const double *tgt, const fmm2d_opts *opts, double *phi, double *dphi, void *ws,
@@ -256,10 +292,15 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     if (!dphi && !(LOG && phi)) return fail(h, FMM2D_EINVAL, "no output requested");
     const int64_t nt = tgt ? n_tgt : 0;
     if (tgt && (n_tgt < 1 || n_tgt > ((int64_t)1 << 30))) return fail(h, FMM2D_EINVAL, "n_tgt out of range");
-    const int mixed = opts->precision == FMM2D_MIXED;
-    const int learned = opts->porder == FMM2D_P_LEARNED;
-    if (learned && (opts->flags & FMM2D_FLAG_REQUIRE_MODEL))
-        return fail(h, FMM2D_ENOMODEL, "learned order requested but no model is loaded");
+    const int mixed = (int)opts->precision;
+    const int learned = opts->porder != FMM2D_P_FIXED;
+    // per-pair orders: the model needs the features' coefficients (k <= FEAT_K)
+    const bool use_model = opts->porder == FMM2D_P_LEARNED && h->d_model && p >= FMM2D_PORDER_FEAT_K;
+    const bool use_given = opts->porder == FMM2D_P_GIVEN;
+    if (opts->porder == FMM2D_P_LEARNED && !use_model && (opts->flags & FMM2D_FLAG_REQUIRE_MODEL))
+        return fail(h, FMM2D_ENOMODEL, h->d_model ? "learned order needs p >= %d" : "no order model is loaded",
+                    FMM2D_PORDER_FEAT_K);
+    if (use_given && !h->given) return fail(h, FMM2D_EINVAL, "FMM2D_P_GIVEN without fmm2d_set_pair_orders");
     fmm_layout lay;
     fmm_plan_layout(n_src, nt, L, p, cap, mixed, learned, &lay);
     if (ws_bytes < lay.total)
@@ -284,11 +325,25 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     ea.L = L; ea.p = p; ea.kernel = (int)opts->kernel; ea.mixed = mixed;
     ea.ns = n_src; ea.nt = nt ? nt : n_src; ea.at_sources = nt == 0;
     ea.ws = w; ea.lay = &lay; ea.binom = h->d_binom; ea.cap = cap; ea.swap = ta.swap;
+    ea.porder = use_model || use_given;
     HIPCHK(h, fmm_p2m(ea, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], st));
     HIPCHK(h, fmm_m2m(ea, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2M], st));
-    // learned order inference would run here
+    if (ea.porder) {
+        fmm_porder_args pa = porder_args(h, w, lay, L, p, cap);
+        if (use_model) {
+            HIPCHK(h, fmm_box_norms(reinterpret_cast<const double2 *>(w + lay.A), pa.radius, p, lay.nb,
+                                    reinterpret_cast<double *>(w + lay.n1), reinterpret_cast<double *>(w + lay.tail),
+                                    st));
+            pa.model = h->d_model;
+            pa.delta = h->delta;
+        } else {
+            pa.given = h->given;
+            pa.ngiven = h->ngiven;
+        }
+        HIPCHK(h, fmm_porder(pa, st));
+    }
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_PORDER], st));
     HIPCHK(h, fmm_m2l(ea, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2L], st));
@@ -308,8 +363,10 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     h->nt = nt;
     h->L = L;
     h->p = p;
+    h->kernel = (int)opts->kernel;
     h->at_sources = nt == 0;
-    h->used_model = 0;
+    h->used_orders = ea.porder;
+    h->used_model = use_model;
     return FMM2D_OK;
 }
 
@@ -338,6 +395,8 @@ extern "C" int fmm2d_sync(fmm2d_handle *h, void *stream)
     HIPCHK(h, hipMemcpy(&s, h->d_status, sizeof(s), hipMemcpyDeviceToHost));
     if (s & FMM_ST_LIST_OVERFLOW)
         return fail(h, FMM2D_ENOSPC, "interaction lists overflowed list_cap; raise fmm2d_opts.list_cap");
+    if (s & FMM_ST_ORDERS_SHORT)
+        return fail(h, FMM2D_EINVAL, "the pair orders given are fewer than the weak pairs");
     return FMM2D_OK;
 }
 
@@ -352,8 +411,8 @@ extern "C" int fmm2d_get_topology(fmm2d_handle *h, fmm2d_topology *t)
     t->p = h->p;
     t->n_src = h->ns;
     t->n_tgt = h->at_sources ? h->ns : h->nt;
-    t->perm = reinterpret_cast<const int32_t *>(w + lay.sl[0]) + 2 * h->ns;
-    t->tperm = h->at_sources ? t->perm : reinterpret_cast<const int32_t *>(w + lay.tl[0]) + 2 * h->nt;
+    t->perm = reinterpret_cast<const int32_t *>(w + lay.perm);
+    t->tperm = h->at_sources ? t->perm : reinterpret_cast<const int32_t *>(w + lay.tperm);
     t->sstart = reinterpret_cast<const int32_t *>(w + lay.sstart);
     t->tstart = h->at_sources ? t->sstart : reinterpret_cast<const int32_t *>(w + lay.tstart);
     t->centre = reinterpret_cast<const double *>(w + lay.centre);
@@ -368,7 +427,7 @@ extern "C" int fmm2d_get_topology(fmm2d_handle *h, fmm2d_topology *t)
     t->p2l_idx = reinterpret_cast<const int32_t *>(w + lay.pidx);
     t->mpole = reinterpret_cast<const double *>(w + lay.A);
     t->local = reinterpret_cast<const double *>(w + lay.B);
-    t->porder = nullptr;
+    t->porder = h->used_orders ? reinterpret_cast<const uint8_t *>(w + lay.qw) : nullptr;
     return FMM2D_OK;
 }
 
@@ -439,5 +498,141 @@ extern "C" int fmm2d_get_stats(fmm2d_handle *h, fmm2d_stats *s)
         HIPCHK(h, e);
     }
     s->used_model = h->used_model;
+    if (h->used_orders && s->n_weak > 0) {
+        uint8_t *q = (uint8_t *)malloc((size_t)s->n_weak);
+        hipError_t e = hipMemcpy(q, h->ws + lay.qw, (size_t)s->n_weak, hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            for (int64_t i = 0; i < s->n_weak; ++i) s->p_hist[q[i]]++;
+        free(q);
+        HIPCHK(h, e);
+    } else {
+        s->p_hist[h->p] = s->n_weak;
+    }
+    return FMM2D_OK;
+}
+
+// ------------------------------------------------------- learned order --
+extern "C" int fmm2d_set_porder_model(fmm2d_handle *h, const float *model, int64_t n_floats, uint32_t schema,
+                                      float delta)
+{
+    if (!h) return FMM2D_EINVAL;
+    HIPCHK(h, hipSetDevice(h->device));
+    if (!model) {
+        if (h->d_model) HIPCHK(h, hipFree(h->d_model));
+        h->d_model = nullptr;
+        return FMM2D_OK;
+    }
+    if (schema != FMM2D_PORDER_SCHEMA) return fail(h, FMM2D_EINVAL, "unknown feature schema %u", schema);
+    if (n_floats != FMM2D_PORDER_MODEL_FLOATS)
+        return fail(h, FMM2D_EINVAL, "model has %lld floats, expected %d", (long long)n_floats,
+                    FMM2D_PORDER_MODEL_FLOATS);
+    for (int64_t i = 0; i < n_floats; ++i)
+        if (!isfinite(model[i]) && i < FMM2D_PORDER_NPARAM + 2 * FMM2D_PORDER_NFEAT)
+            return fail(h, FMM2D_EINVAL, "model entry %lld is not finite", (long long)i);
+    if (!isfinite(delta)) return fail(h, FMM2D_EINVAL, "delta is not finite");
+    if (!h->d_model) HIPCHK(h, hipMalloc((void **)&h->d_model, sizeof(float) * FMM2D_PORDER_MODEL_FLOATS));
+    HIPCHK(h, hipMemcpy(h->d_model, model, sizeof(float) * FMM2D_PORDER_MODEL_FLOATS, hipMemcpyHostToDevice));
+    h->delta = delta;
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_set_pair_orders(fmm2d_handle *h, const uint8_t *orders, int64_t n)
+{
+    if (!h) return FMM2D_EINVAL;
+    if (orders && n < 0) return fail(h, FMM2D_EINVAL, "negative count");
+    h->given = orders;
+    h->ngiven = orders ? n : 0;
+    return FMM2D_OK;
+}
+
+// weak-pair count of the last evaluation (synchronises its stream)
+static int last_nweak(fmm2d_handle *h, int64_t *nw)
+{
+    HIPCHK(h, hipStreamSynchronize(h->last_stream));
+    int32_t wend = 0;
+    const int32_t *woff = reinterpret_cast<const int32_t *>(h->ws + h->lay.woff);
+    HIPCHK(h, hipMemcpy(&wend, woff + start_off(h->L) + nbox(h->L), 4, hipMemcpyDeviceToHost));
+    *nw = wend;
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_pair_features(fmm2d_handle *h, float *feat, int64_t n_cap, void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    if (!h->have_topo) return fail(h, FMM2D_EINVAL, "no evaluation yet");
+    if (!feat || n_cap < 0) return fail(h, FMM2D_EINVAL, "bad feature buffer");
+    if (h->p < FMM2D_PORDER_FEAT_K)
+        return fail(h, FMM2D_EINVAL, "features need an evaluation at p >= %d", FMM2D_PORDER_FEAT_K);
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    char *w = const_cast<char *>(h->ws);
+    const fmm_layout &lay = h->lay;
+    fmm_porder_args pa = porder_args(h, w, lay, h->L, h->p, h->lay.cap);
+    HIPCHK(h, fmm_box_norms(reinterpret_cast<const double2 *>(w + lay.A), pa.radius, h->p, lay.nb,
+                            reinterpret_cast<double *>(w + lay.n1), reinterpret_cast<double *>(w + lay.tail), st));
+    HIPCHK(h, fmm_features(pa, n_cap, feat, st));
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_pair_labels(fmm2d_handle *h, const double *val, double tol, int32_t qmin, int32_t qmax,
+                                 uint8_t *labels, int64_t n_cap, void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    if (!h->have_topo) return fail(h, FMM2D_EINVAL, "no evaluation yet");
+    if (!val || !labels || n_cap < 0) return fail(h, FMM2D_EINVAL, "bad buffers");
+    if (!(tol > 0.0)) return fail(h, FMM2D_EINVAL, "tol must be > 0");
+    if (h->used_orders) return fail(h, FMM2D_EINVAL, "labels need an evaluation at one fixed order");
+    if (h->p > 63) return fail(h, FMM2D_EINVAL, "labels need p <= 63");
+    if (qmin < 0 || qmax < qmin || qmax > h->p)
+        return fail(h, FMM2D_EINVAL, "need 0 <= qmin <= qmax <= p (%d)", h->p);
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    char *w = const_cast<char *>(h->ws);
+    const fmm_layout &lay = h->lay;
+    fmm_porder_args pa = porder_args(h, w, lay, h->L, h->p, h->lay.cap);
+    const int32_t *tperm = reinterpret_cast<const int32_t *>(w + (h->at_sources ? lay.perm : lay.tperm));
+    const int32_t *tstart = reinterpret_cast<const int32_t *>(w + (h->at_sources ? lay.sstart : lay.tstart));
+    HIPCHK(h, fmm_labels(pa, reinterpret_cast<const double2 *>(w + lay.A), h->d_binom, tperm, tstart, val, tol, h->p,
+                         h->kernel, qmin, qmax, n_cap, reinterpret_cast<double *>(w + lay.vmin),
+                         reinterpret_cast<double *>(w + lay.budget), labels, st));
+    return FMM2D_OK;
+}
+
+extern "C" size_t fmm2d_mlp_work_size(int64_t n)
+{
+    return n < 0 ? 0 : (size_t)fmm_mlp_grad_blocks(n) * (FMM2D_PORDER_NPARAM + 1) * sizeof(float) + 256;
+}
+
+extern "C" int fmm2d_mlp_forward(fmm2d_handle *h, const float *model, const float *x, int64_t n, float *y,
+                                 void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    if (!model || n < 0 || (n > 0 && (!x || !y))) return fail(h, FMM2D_EINVAL, "bad arguments");
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, fmm_mlp_forward(model, x, n, y, (hipStream_t)stream));
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_mlp_grad(fmm2d_handle *h, const float *model, const float *x, const float *q, int64_t n,
+                              float tau, float *grad, float *loss, void *work, size_t work_bytes, void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    if (!model || !grad || n < 1 || !x || !q || !work) return fail(h, FMM2D_EINVAL, "bad arguments");
+    if (!(tau > 0.0f && tau < 1.0f)) return fail(h, FMM2D_EINVAL, "tau must be in (0,1)");
+    if (work_bytes < fmm2d_mlp_work_size(n)) return fail(h, FMM2D_ENOSPC, "work buffer too small");
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, fmm_mlp_grad(model, x, q, n, tau, (float *)work, grad, loss, (hipStream_t)stream));
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_mlp_adam(fmm2d_handle *h, float *model, const float *grad, float *m, float *v, int32_t step,
+                              float lr, float beta1, float beta2, float eps, void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    if (!model || !grad || !m || !v || step < 1) return fail(h, FMM2D_EINVAL, "bad arguments");
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(h, FMM2D_EINVAL, "bad Adam hyper-parameters");
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, fmm_mlp_adam(model, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream));
     return FMM2D_OK;
 }

@@ -117,9 +117,30 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_down(const int32_t *__restrict_
     }
 }
 
+// Small arrays: one block of 1024 threads walks the array in chunks.
+__global__ void __launch_bounds__(1024) k_scan_single(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                       int64_t n, const int32_t *__restrict__ base)
+{
+    __shared__ int32_t sh[1024 / WAVE];
+    int32_t carry = base ? *base : 0;
+    for (int64_t c = 0; c < n; c += blockDim.x) {
+        const int64_t k = c + threadIdx.x;
+        const int32_t v = k < n ? in[k] : 0;
+        int32_t tot;
+        const int32_t ex = block_excl_scan(v, sh, &tot);
+        if (k < n) out[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 hipError_t fmm_scan_i32(const int32_t *in, int32_t *out, int64_t n, const int32_t *base,
                         int32_t *blocksums, hipStream_t st)
 {
+    if (n <= 16384) {
+        k_scan_single<<<1, 1024, 0, st>>>(in, out, n, base);
+        return hipGetLastError();
+    }
     int64_t nb = fmm_scan_blocks(n);
     if (nb > 0) k_scan_reduce<<<(unsigned)nb, SCAN_T, 0, st>>>(in, n, blocksums);
     k_scan_sums<<<1, 1024, 0, st>>>(blocksums, nb, base, out + n);
@@ -216,18 +237,17 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
     }
 }
 
-// Sort indices 0..n-1 of pts by (coordinate `axis`, index) into out.
-static hipError_t presort(const double *pts, int64_t n, int axis, uint64_t *k0, uint64_t *k1,
-                          int32_t *v0, int32_t *v1, int32_t *hist, int32_t *bsum, int32_t *out,
-                          hipStream_t st)
+// LSD radix sort of (k0, v0) over `passes` 8-bit digits (ping-pong through
+// k1, v1); the values end up in out.  Stable, so equal keys keep their order.
+static hipError_t radix_sort(int64_t n, int passes, uint64_t *k0, uint64_t *k1, int32_t *v0, int32_t *v1,
+                             int32_t *hist, int32_t *bsum, int32_t *out, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    k_rs_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pts, n, axis, k0, v0);
-    int nblk = (int)((n + RS_BLOCK - 1) / RS_BLOCK);
+    const int nblk = (int)((n + RS_BLOCK - 1) / RS_BLOCK);
     uint64_t *ka = k0, *kb = k1;
     int32_t *va = v0, *vb = v1;
-    for (int pass = 0; pass < 8; ++pass) {
-        int shift = 8 * pass;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
         k_rs_hist<<<nblk, RS_T, 0, st>>>(ka, n, shift, hist, nblk);
         hipError_t e = fmm_scan_i32(hist, hist, (int64_t)256 * nblk, nullptr, bsum, st);
         if (e != hipSuccess) return e;
@@ -238,27 +258,51 @@ static hipError_t presort(const double *pts, int64_t n, int axis, uint64_t *k0, 
     return hipMemcpyAsync(out, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
 }
 
-// ------------------------------------------------------------ splits --
-// Segment j of a step holds positions [start[j], start[j+1]).  Position ->
-// segment by binary search (empty segments are skipped: the largest j with
-// start[j] <= i).
-__device__ __forceinline__ int32_t seg_of(const int32_t *__restrict__ start, int32_t nseg, int64_t i)
+// Indices 0..n-1 of pts ordered by (coordinate `axis`, index).
+static hipError_t presort(const double *pts, int64_t n, int axis, uint64_t *k0, uint64_t *k1,
+                          int32_t *v0, int32_t *v1, int32_t *hist, int32_t *bsum, int32_t *out,
+                          hipStream_t st)
 {
-    int32_t lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        int32_t mid = (lo + hi + 1) >> 1;
-        if ((int64_t)start[mid] <= i) lo = mid; else hi = mid - 1;
+    if (n <= 0) return hipSuccess;
+    k_rs_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pts, n, axis, k0, v0);
+    return radix_sort(n, 8, k0, k1, v0, v1, hist, bsum, out, st);
+}
+
+// ------------------------------------------------------------ splits --
+// Every point set is kept as two lists of self-describing records, one in
+// (x, index) order and one in (y, index) order inside every segment.  A record
+// carries its coordinates, original index and current segment, so the side of
+// a split follows from comparing the record with its segment's pivot: no
+// gathers through the original index, and stable partitions keep both lists
+// sorted inside every new segment.
+struct pt_rec {
+    double x, y;
+    int32_t idx, seg;
+};
+
+__global__ void k_rec_init(const double *__restrict__ pts, const int32_t *__restrict__ order, int64_t n,
+                           pt_rec *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int32_t v = order[i];
+        pt_rec r;
+        r.x = pts[2 * (int64_t)v];
+        r.y = pts[2 * (int64_t)v + 1];
+        r.idx = v;
+        r.seg = 0;
+        out[i] = r;
     }
-    return lo;
 }
 
 struct seg_args {
-    const double *src, *tgt;
-    const int32_t *slx, *sly;     // source lists sorted by x / y within segments
-    const int32_t *tlx, *tly;     // target lists (nt > 0)
+    const pt_rec *slx, *sly;      // source lists
+    const pt_rec *tlx, *tly;      // target lists (nt > 0)
     const int32_t *sst, *tst;     // step starts (nseg+1)
     int32_t *sst_next, *tst_next; // next step starts (2 nseg + 1), or NULL
     uint8_t *axis;
+    double *pc;                   // pivot coordinate per segment
+    int32_t *pi;                  // pivot index per segment
     int32_t *nlo, *tlo;
     double *centre, *radius;      // level arrays (already offset), or NULL
     int32_t *lvl_sst, *lvl_tst;   // per-level start output (already offset), or NULL
@@ -267,7 +311,8 @@ struct seg_args {
 };
 
 // One thread per segment: tight rectangle of its sources and targets, box
-// geometry (on even steps), split axis, median rank and target split count.
+// geometry (on even steps), split axis, pivot (the record at rank floor(n/2)
+// of the axis list) and the number of targets below the pivot coordinate.
 __global__ void k_seg(seg_args a)
 {
     int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -278,17 +323,17 @@ __global__ void k_seg(seg_args a)
     const int32_t m = t1 - t0;
     double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
     if (n > 0) {
-        x0 = a.src[2 * (int64_t)a.slx[s0]];
-        x1 = a.src[2 * (int64_t)a.slx[s1 - 1]];
-        y0 = a.src[2 * (int64_t)a.sly[s0] + 1];
-        y1 = a.src[2 * (int64_t)a.sly[s1 - 1] + 1];
+        x0 = a.slx[s0].x;
+        x1 = a.slx[s1 - 1].x;
+        y0 = a.sly[s0].y;
+        y1 = a.sly[s1 - 1].y;
     }
     if (m > 0) {
         double u;
-        u = a.tgt[2 * (int64_t)a.tlx[t0]];          if (u < x0) x0 = u;
-        u = a.tgt[2 * (int64_t)a.tlx[t1 - 1]];      if (u > x1) x1 = u;
-        u = a.tgt[2 * (int64_t)a.tly[t0] + 1];      if (u < y0) y0 = u;
-        u = a.tgt[2 * (int64_t)a.tly[t1 - 1] + 1];  if (u > y1) y1 = u;
+        u = a.tlx[t0].x;      if (u < x0) x0 = u;
+        u = a.tlx[t1 - 1].x;  if (u > x1) x1 = u;
+        u = a.tly[t0].y;      if (u < y0) y0 = u;
+        u = a.tly[t1 - 1].y;  if (u > y1) y1 = u;
     }
     const double w = x1 - x0, h = y1 - y0;
     if (a.centre) {
@@ -308,18 +353,26 @@ __global__ void k_seg(seg_args a)
     const int ax = (w >= h) ? 0 : 1;
     const int32_t nl = n / 2;
     int32_t tl = 0;
+    double pcv = 0.0;
+    int32_t piv = 0;
+    if (n > 0) {
+        const pt_rec P = (ax ? a.sly : a.slx)[s0 + nl];
+        pcv = ax ? P.y : P.x;
+        piv = P.idx;
+    }
     if (n > 0 && m > 0) {
-        const int32_t *A = ax ? a.sly : a.slx;
-        const double sv = a.src[2 * (int64_t)A[s0 + nl] + ax];
-        const int32_t *TA = ax ? a.tly : a.tlx;
-        int32_t lo = t0, hi = t1; // first position with coordinate >= sv
+        const pt_rec *TA = ax ? a.tly : a.tlx;
+        int32_t lo = t0, hi = t1; // first position with coordinate >= pivot coordinate
         while (lo < hi) {
             int32_t mid = lo + ((hi - lo) >> 1);
-            if (a.tgt[2 * (int64_t)TA[mid] + ax] >= sv) hi = mid; else lo = mid + 1;
+            const double c = ax ? TA[mid].y : TA[mid].x;
+            if (c >= pcv) hi = mid; else lo = mid + 1;
         }
         tl = lo - t0;
     }
     a.axis[j] = (uint8_t)ax;
+    a.pc[j] = pcv;
+    a.pi[j] = piv;
     a.nlo[j] = nl;
     a.tlo[j] = tl;
     a.sst_next[2 * j] = s0;
@@ -332,45 +385,49 @@ __global__ void k_seg(seg_args a)
     }
 }
 
-// Side flag (0 = lo, 1 = hi) of every original index, from the axis list of
-// its segment: the first nlo positions are lo.
-__global__ void k_mark(const int32_t *__restrict__ lx, const int32_t *__restrict__ ly,
-                       const int32_t *__restrict__ start, int32_t nseg,
-                       const uint8_t *__restrict__ axis, const int32_t *__restrict__ nlo,
-                       int64_t n, uint8_t *__restrict__ side)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t j = seg_of(start, nseg, i);
-    const int32_t *A = axis[j] ? ly : lx;
-    side[A[i]] = (i - start[j] < nlo[j]) ? 0 : 1;
-}
-
 struct part_list {
-    const int32_t *in;
-    int32_t *out;
+    const pt_rec *in;
+    pt_rec *out;
     int32_t *bsum;        // nblk + 1
-    const uint8_t *side;
     const int32_t *start; // segment starts (nseg + 1)
     const int32_t *nlo;   // lo count per segment
     const int32_t *LO;    // exclusive scan of nlo
     int64_t n;
     int32_t nseg;
+    int target;           // targets: lo iff coordinate < pivot coordinate
 };
 struct part_batch {
-    part_list l[6];
+    part_list l[4];
+    const uint8_t *axis;
+    const double *pc;
+    const int32_t *pi;
 };
 
+// Side of a record: sources go lo iff (coordinate, index) < pivot, targets
+// iff coordinate < pivot coordinate.
+__device__ __forceinline__ bool rec_lo(const part_batch &pb, const part_list &p, const pt_rec &r)
+{
+    const int32_t j = min(max(r.seg, 0), p.nseg - 1);
+    const double c = pb.axis[j] ? r.y : r.x;
+    const double pc = pb.pc[j];
+    if (p.target) return c < pc;
+    return c < pc || (c == pc && r.idx < pb.pi[j]);
+}
+
+// Records are read striped (record base + i*SCAN_T + thread) so that the
+// lanes of a wave touch consecutive records.
 __global__ void __launch_bounds__(SCAN_T) k_part_reduce(part_batch pb)
 {
     const part_list &p = pb.l[blockIdx.y];
     __shared__ int32_t sh[SCAN_T / WAVE];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
     if ((int64_t)blockIdx.x * SCAN_B >= p.n) return; // whole block idle (uniform)
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
     int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_I; ++i)
-        if (base + i < p.n) s += p.side[p.in[base + i]] == 0;
+    for (int i = 0; i < SCAN_I; ++i) {
+        const int64_t k = base + (int64_t)i * SCAN_T;
+        if (k < p.n) s += rec_lo(pb, p, p.in[k]);
+    }
     int32_t tot;
     block_excl_scan(s, sh, &tot);
     if (threadIdx.x == 0) p.bsum[blockIdx.x] = tot;
@@ -395,33 +452,55 @@ __global__ void __launch_bounds__(1024) k_part_sums(part_batch pb)
 __global__ void __launch_bounds__(SCAN_T) k_part_scatter(part_batch pb)
 {
     const part_list &p = pb.l[blockIdx.y];
-    __shared__ int32_t sh[SCAN_T / WAVE];
+    __shared__ int32_t wtot[SCAN_T / WAVE];
     if ((int64_t)blockIdx.x * SCAN_B >= p.n) return;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
-    int32_t v[SCAN_I];
-    uint8_t lo[SCAN_I];
-    int32_t s = 0;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
+    int32_t carry = p.bsum[blockIdx.x]; // lo records before this block
 #pragma unroll
     for (int i = 0; i < SCAN_I; ++i) {
-        v[i] = (base + i < p.n) ? p.in[base + i] : 0;
-        lo[i] = (base + i < p.n) ? (p.side[v[i]] == 0) : 0;
-        s += lo[i];
-    }
-    int32_t tot;
-    int32_t run = block_excl_scan(s, sh, &tot) + p.bsum[blockIdx.x];
-#pragma unroll
-    for (int i = 0; i < SCAN_I; ++i) {
-        int64_t pos = base + i;
-        if (pos < p.n) {
-            int32_t j = seg_of(p.start, p.nseg, pos);
-            int32_t st = p.start[j];
-            int32_t rank = run - p.LO[j]; // lo elements before pos in segment j
-            int64_t dst = lo[i] ? (int64_t)st + rank
-                                : (int64_t)st + p.nlo[j] + (pos - st - rank);
-            dst = dst < 0 ? 0 : (dst >= p.n ? p.n - 1 : dst); // never leave the array
-            p.out[dst] = v[i];
+        const int64_t pos = base + (int64_t)i * SCAN_T;
+        const bool act = pos < p.n;
+        pt_rec r;
+        bool lo = false;
+        if (act) {
+            r = p.in[pos];
+            lo = rec_lo(pb, p, r);
         }
-        run += lo[i];
+        const uint64_t m = __ballot(lo);
+        if (lane == 0) wtot[w] = __popcll(m);
+        __syncthreads();
+        int32_t before = carry + __popcll(m & lt), stripe = 0;
+        for (int q = 0; q < SCAN_T / WAVE; ++q) {
+            const int32_t t = wtot[q];
+            before += (q < w) ? t : 0;
+            stripe += t;
+        }
+        __syncthreads();
+        carry += stripe;
+        if (act) {
+            const int32_t j = min(max(r.seg, 0), p.nseg - 1);
+            const int32_t st = p.start[j];
+            const int32_t rank = before - p.LO[j]; // lo records before pos in segment j
+            int64_t dst = lo ? (int64_t)st + rank : (int64_t)st + p.nlo[j] + (pos - st - rank);
+            dst = dst < 0 ? 0 : (dst >= p.n ? p.n - 1 : dst); // never leave the array
+            r.seg = 2 * j + (lo ? 0 : 1);
+            p.out[dst] = r;
+        }
+    }
+}
+
+// Leaf of every original index (as the sort key) and the identity values.
+__global__ void k_leaf_keys(const pt_rec *__restrict__ lx, int64_t n, uint64_t *__restrict__ keys,
+                            int32_t *__restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const pt_rec r = lx[i];
+        const int64_t v = min(max((int64_t)r.idx, (int64_t)0), n - 1);
+        keys[v] = (uint64_t)(uint32_t)r.seg;
+        vals[i] = (int32_t)i;
     }
 }
 
@@ -596,36 +675,34 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     int32_t *v0 = WS(int32_t, lay.vals[0]), *v1 = WS(int32_t, lay.vals[1]);
     int32_t *hist = WS(int32_t, lay.hist);
     int32_t *bsum = WS(int32_t, lay.bsum);
-    // list buffers: [0..2] current lx, ly, li; [3..5] partition outputs
-    int32_t *sl[6], *tl[6];
-    for (int i = 0; i < 6; ++i) {
-        sl[i] = WS(int32_t, lay.sl[0]) + (int64_t)i * ns;
-        tl[i] = nt ? WS(int32_t, lay.tl[0]) + (int64_t)i * nt : nullptr;
+    int32_t *perm = WS(int32_t, lay.perm), *tperm = nt ? WS(int32_t, lay.tperm) : nullptr;
+    // record lists: [0] x-ordered, [1] y-ordered, [2], [3] partition outputs
+    pt_rec *sl[4], *tl[4];
+    for (int i = 0; i < 4; ++i) {
+        sl[i] = WS(pt_rec, lay.srec) + (int64_t)i * ns;
+        tl[i] = nt ? WS(pt_rec, lay.trec) + (int64_t)i * nt : nullptr;
     }
-    uint8_t *sside = WS(uint8_t, lay.sside), *tside = nt ? WS(uint8_t, lay.tside) : nullptr;
     int32_t *sstep = WS(int32_t, lay.sstep), *tstep = WS(int32_t, lay.tstep);
     uint8_t *axis = WS(uint8_t, lay.seg_axis);
+    double *pc = WS(double, lay.seg_pc);
+    int32_t *pi = WS(int32_t, lay.seg_pi);
     int32_t *nlo = WS(int32_t, lay.seg_nlo), *tlo = WS(int32_t, lay.seg_tlo);
     int32_t *LO = WS(int32_t, lay.seg_LO), *TLO = WS(int32_t, lay.seg_TLO);
     int32_t *sstart = WS(int32_t, lay.sstart), *tstart = WS(int32_t, lay.tstart);
     double *centre = WS(double, lay.centre), *radius = WS(double, lay.radius);
 
-    // presort: x- and y-ordered lists; index-ordered list
-    CK(presort(a.src, ns, 0, k0, k1, v0, v1, hist, bsum, sl[0], st));
-    CK(presort(a.src, ns, 1, k0, k1, v0, v1, hist, bsum, sl[1], st));
+    // presort into (coordinate, index) order, then records
+    CK(presort(a.src, ns, 0, k0, k1, v0, v1, hist, bsum, perm, st));
+    k_rec_init<<<nblk256(ns), 256, 0, st>>>(a.src, perm, ns, sl[0]);
+    CK(presort(a.src, ns, 1, k0, k1, v0, v1, hist, bsum, perm, st));
+    k_rec_init<<<nblk256(ns), 256, 0, st>>>(a.src, perm, ns, sl[1]);
     if (nt) {
-        CK(presort(a.tgt, nt, 0, k0, k1, v0, v1, hist, bsum, tl[0], st));
-        CK(presort(a.tgt, nt, 1, k0, k1, v0, v1, hist, bsum, tl[1], st));
+        CK(presort(a.tgt, nt, 0, k0, k1, v0, v1, hist, bsum, tperm, st));
+        k_rec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[0]);
+        CK(presort(a.tgt, nt, 1, k0, k1, v0, v1, hist, bsum, tperm, st));
+        k_rec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[1]);
     }
-    // identity lists and the root segment
-    {
-        int64_t nmax = ns > nt ? ns : nt;
-        // k_rs_init writes vals = identity; reuse it through a tiny lambda-free kernel
-        k_rs_init<<<nblk256(ns), 256, 0, st>>>(a.src, ns, 0, k0, sl[2]);
-        if (nt) k_rs_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, nt, 0, k0, tl[2]);
-        (void)nmax;
-        k_root<<<1, 1, 0, st>>>(sstep, (int32_t)ns, tstep, (int32_t)nt);
-    }
+    k_root<<<1, 1, 0, st>>>(sstep, (int32_t)ns, tstep, (int32_t)nt);
     int64_t soff_k = 0; // offset of step k's starts
     for (int k = 0; k <= 2 * L; ++k) {
         const int32_t nseg = (int32_t)(((int64_t)1) << k);
@@ -633,13 +710,12 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         const bool even = (k % 2) == 0;
         const int l = k / 2;
         seg_args sa;
-        sa.src = a.src; sa.tgt = a.tgt;
         sa.slx = sl[0]; sa.sly = sl[1];
         sa.tlx = tl[0]; sa.tly = tl[1];
         sa.sst = sstep + soff_k; sa.tst = tstep + soff_k;
         sa.sst_next = split ? sstep + soff_k + nseg + 1 : nullptr;
         sa.tst_next = split ? tstep + soff_k + nseg + 1 : nullptr;
-        sa.axis = axis; sa.nlo = nlo; sa.tlo = tlo;
+        sa.axis = axis; sa.pc = pc; sa.pi = pi; sa.nlo = nlo; sa.tlo = tlo;
         sa.centre = even ? centre + 2 * box_off(l) : nullptr;
         sa.radius = even ? radius + box_off(l) : nullptr;
         sa.lvl_sst = even ? sstart + start_off(l) : nullptr;
@@ -651,27 +727,25 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         // exclusive scans of the lo counts over segments
         CK(fmm_scan_i32(nlo, LO, nseg, nullptr, hist, st));
         if (nt) CK(fmm_scan_i32(tlo, TLO, nseg, nullptr, hist, st));
-        k_mark<<<nblk256(ns), 256, 0, st>>>(sl[0], sl[1], sstep + soff_k, nseg, axis, nlo, ns, sside);
-        if (nt)
-            k_mark<<<nblk256(nt), 256, 0, st>>>(tl[0], tl[1], tstep + soff_k, nseg, axis, tlo, nt, tside);
         part_batch pb;
+        pb.axis = axis; pb.pc = pc; pb.pi = pi;
         int nl = 0;
-        int64_t bsum_stride = fmm_scan_blocks(ns > nt ? ns : nt) + 1;
-        for (int q = 0; q < 3; ++q) {
+        const int64_t bsum_stride = fmm_scan_blocks(ns > nt ? ns : nt) + 1;
+        for (int q = 0; q < 2; ++q) {
             part_list &p = pb.l[nl];
-            p.in = sl[q]; p.out = sl[3 + q];
+            p.in = sl[q]; p.out = sl[2 + q];
             p.bsum = bsum + (int64_t)nl * bsum_stride;
-            p.side = sside; p.start = sstep + soff_k; p.nlo = nlo; p.LO = LO;
-            p.n = ns; p.nseg = nseg;
+            p.start = sstep + soff_k; p.nlo = nlo; p.LO = LO;
+            p.n = ns; p.nseg = nseg; p.target = 0;
             ++nl;
         }
         if (nt) {
-            for (int q = 0; q < 3; ++q) {
+            for (int q = 0; q < 2; ++q) {
                 part_list &p = pb.l[nl];
-                p.in = tl[q]; p.out = tl[3 + q];
+                p.in = tl[q]; p.out = tl[2 + q];
                 p.bsum = bsum + (int64_t)nl * bsum_stride;
-                p.side = tside; p.start = tstep + soff_k; p.nlo = tlo; p.LO = TLO;
-                p.n = nt; p.nseg = nseg;
+                p.start = tstep + soff_k; p.nlo = tlo; p.LO = TLO;
+                p.n = nt; p.nseg = nseg; p.target = 1;
                 ++nl;
             }
         }
@@ -681,33 +755,30 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         k_part_sums<<<nl, 1024, 0, st>>>(pb);
         k_part_scatter<<<g, SCAN_T, 0, st>>>(pb);
         CK(hipGetLastError());
-        for (int q = 0; q < 3; ++q) {
-            int32_t *t = sl[q]; sl[q] = sl[3 + q]; sl[3 + q] = t;
-            if (nt) { t = tl[q]; tl[q] = tl[3 + q]; tl[3 + q] = t; }
+        for (int q = 0; q < 2; ++q) {
+            pt_rec *t = sl[q]; sl[q] = sl[2 + q]; sl[2 + q] = t;
+            if (nt) { t = tl[q]; tl[q] = tl[2 + q]; tl[2 + q] = t; }
         }
         soff_k += nseg + 1;
     }
-    // perm / tperm: the index-ordered lists, gathered points
-    int32_t *perm = sl[2];
-    int32_t *tperm = nt ? tl[2] : nullptr;
-    if (perm != WS(int32_t, lay.sl[0]) + 2 * ns) {
-        CK(hipMemcpyAsync(WS(int32_t, lay.sl[0]) + 2 * ns, perm, (size_t)ns * 4,
-                          hipMemcpyDeviceToDevice, st));
+    // leaf order with ascending original index inside every leaf: a stable
+    // sort of the identity by leaf number
+    const int passes = (2 * L + 7) / 8;
+    k_leaf_keys<<<nblk256(ns), 256, 0, st>>>(sl[0], ns, k0, v0);
+    if (passes > 0) CK(radix_sort(ns, passes, k0, k1, v0, v1, hist, bsum, perm, st));
+    else CK(hipMemcpyAsync(perm, v0, (size_t)ns * 4, hipMemcpyDeviceToDevice, st));
+    if (nt) {
+        k_leaf_keys<<<nblk256(nt), 256, 0, st>>>(tl[0], nt, k0, v0);
+        if (passes > 0) CK(radix_sort(nt, passes, k0, k1, v0, v1, hist, bsum, tperm, st));
+        else CK(hipMemcpyAsync(tperm, v0, (size_t)nt * 4, hipMemcpyDeviceToDevice, st));
     }
-    if (nt && tperm != WS(int32_t, lay.tl[0]) + 2 * nt) {
-        CK(hipMemcpyAsync(WS(int32_t, lay.tl[0]) + 2 * nt, tperm, (size_t)nt * 4,
-                          hipMemcpyDeviceToDevice, st));
-    }
-    perm = WS(int32_t, lay.sl[0]) + 2 * ns;
-    tperm = nt ? WS(int32_t, lay.tl[0]) + 2 * nt : nullptr;
     {
         int64_t nmax = ns > nt ? ns : nt;
         k_gather<<<nblk256(nmax), 256, 0, st>>>(a.src, m, perm, ns, WS(double4, lay.srcs),
-                                                lay.mixed ? WS(float2, lay.m32) : nullptr, a.tgt,
+                                                lay.mixed == 1 ? WS(float2, lay.m32) : nullptr, a.tgt,
                                                 tperm, nt, nt ? WS(double2, lay.tgts) : nullptr);
         CK(hipGetLastError());
     }
-
     return hipSuccess;
 }
 

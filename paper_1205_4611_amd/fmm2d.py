@@ -17,17 +17,29 @@ LIB_PATH = os.path.join(_HERE, "libfmm2d.so")
 
 OK, EINVAL, ENOSPC, EHIP, ENOMODEL = 0, -1, -2, -3, -4
 KERNEL = {"log": 1, "harmonic": 2}
-PRECISION = {"fp64": 0, "mixed": 1}
-PORDER = {"fixed": 0, "learned": 1}
+PRECISION = {"fp64": 0, "mixed": 1, "mixed_far": 2}
+PORDER = {"fixed": 0, "learned": 1, "given": 2}
 FLAG_TIMING = 1
 FLAG_REQUIRE_MODEL = 2
 FLAG_LEAF_SWAP = 4
 PHASES = ("tree", "lists", "p2m", "m2m", "porder", "m2l", "l2l", "p2l", "p2p")
 
+# learned order (see include/fmm2d.h)
+PORDER_SCHEMA = 1
+PORDER_NFEAT = 8
+PORDER_HIDDEN = 32
+PORDER_NPARAM = 321
+PORDER_MODEL_FLOATS = 353
+PORDER_FEAT_K = 20
+PORDER_QMIN = 4
+
 #: every symbol include/fmm2d.h declares
 EXPORTS = ("fmm2d_default_opts", "fmm2d_create", "fmm2d_destroy", "fmm2d_last_error",
            "fmm2d_nlevels", "fmm2d_workspace_size", "fmm2d_eval", "fmm2d_direct",
-           "fmm2d_sync", "fmm2d_get_topology", "fmm2d_get_stats")
+           "fmm2d_sync", "fmm2d_get_topology", "fmm2d_get_stats",
+           "fmm2d_set_porder_model", "fmm2d_set_pair_orders", "fmm2d_pair_features",
+           "fmm2d_pair_labels", "fmm2d_mlp_work_size", "fmm2d_mlp_forward", "fmm2d_mlp_grad",
+           "fmm2d_mlp_adam")
 
 
 class Opts(ctypes.Structure):
@@ -90,6 +102,23 @@ def load():
     lib.fmm2d_get_topology.restype = ctypes.c_int
     lib.fmm2d_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.fmm2d_get_stats.restype = ctypes.c_int
+    f32 = ctypes.c_float
+    lib.fmm2d_set_porder_model.argtypes = [P, P, i64, u32, f32]
+    lib.fmm2d_set_porder_model.restype = ctypes.c_int
+    lib.fmm2d_set_pair_orders.argtypes = [P, P, i64]
+    lib.fmm2d_set_pair_orders.restype = ctypes.c_int
+    lib.fmm2d_pair_features.argtypes = [P, P, i64, P]
+    lib.fmm2d_pair_features.restype = ctypes.c_int
+    lib.fmm2d_pair_labels.argtypes = [P, P, ctypes.c_double, i32, i32, P, i64, P]
+    lib.fmm2d_pair_labels.restype = ctypes.c_int
+    lib.fmm2d_mlp_work_size.argtypes = [i64]
+    lib.fmm2d_mlp_work_size.restype = ctypes.c_size_t
+    lib.fmm2d_mlp_forward.argtypes = [P, P, P, i64, P, P]
+    lib.fmm2d_mlp_forward.restype = ctypes.c_int
+    lib.fmm2d_mlp_grad.argtypes = [P, P, P, P, i64, f32, P, P, P, ctypes.c_size_t, P]
+    lib.fmm2d_mlp_grad.restype = ctypes.c_int
+    lib.fmm2d_mlp_adam.argtypes = [P, P, P, P, P, i32, f32, f32, f32, f32, P]
+    lib.fmm2d_mlp_adam.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -250,6 +279,105 @@ class FMM2D:
                 "n_p2p_pairs": st.n_p2p_pairs, "status": st.status,
                 "used_model": st.used_model, "p_hist": list(st.p_hist)}
 
+    # ---- per-interaction orders -------------------------------------------
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(torch.device("cuda", self.device)).cuda_stream)
+
+    def _cuda_f32(self, t, n=None, name="tensor"):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+            raise TypeError("%s must be a float32 CUDA tensor" % name)
+        if n is not None and t.numel() != n:
+            raise ValueError("%s must have %d entries" % (name, n))
+        return t.contiguous()
+
+    def set_porder_model(self, model, delta: float = 0.0):
+        """Load an order model (FMM2D_PORDER_MODEL_FLOATS host floats), or
+        drop it with model=None."""
+        import numpy as np
+        if model is None:
+            rc = self.lib.fmm2d_set_porder_model(self.h, None, 0, PORDER_SCHEMA, 0.0)
+        else:
+            w = np.ascontiguousarray(np.asarray(model, dtype=np.float32).ravel())
+            rc = self.lib.fmm2d_set_porder_model(self.h, w.ctypes.data_as(ctypes.c_void_p), w.size,
+                                                 PORDER_SCHEMA, float(delta))
+        if rc != OK:
+            raise self._err(rc)
+
+    def set_pair_orders(self, orders):
+        """Orders for porder="given" evaluations: a uint8 CUDA tensor in
+        weak-list order (kept alive by this object), or None."""
+        if orders is None:
+            self._orders = None
+            rc = self.lib.fmm2d_set_pair_orders(self.h, None, 0)
+        else:
+            if not isinstance(orders, torch.Tensor) or not orders.is_cuda or orders.dtype != torch.uint8:
+                raise TypeError("orders must be a uint8 CUDA tensor")
+            self._orders = orders.contiguous()
+            rc = self.lib.fmm2d_set_pair_orders(self.h, _ptr(self._orders), self._orders.numel())
+        if rc != OK:
+            raise self._err(rc)
+
+    def pair_features(self):
+        """Features [n_weak, 8] (float32, CUDA) of the last evaluation."""
+        n = self.stats()["n_weak"]
+        feat = torch.empty((max(n, 1), PORDER_NFEAT), dtype=torch.float32, device="cuda:%d" % self.device)
+        rc = self.lib.fmm2d_pair_features(self.h, _ptr(feat), n, self._stream())
+        if rc != OK:
+            raise self._err(rc)
+        self.sync()
+        return feat[:n]
+
+    def pair_labels(self, val, tol: float, qmin: int = PORDER_QMIN, qmax: int = 30):
+        """Labels (uint8 CUDA [n_weak]) of the last evaluation; val is the
+        complex128 CUDA output of that evaluation (Phi for log, Phi' for
+        harmonic) in the caller's target order."""
+        n = self.stats()["n_weak"]
+        lab = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda:%d" % self.device)
+        v = torch.view_as_real(val.contiguous())
+        rc = self.lib.fmm2d_pair_labels(self.h, _ptr(v), float(tol), int(qmin), int(qmax), _ptr(lab), n,
+                                        self._stream())
+        if rc != OK:
+            raise self._err(rc)
+        self.sync()
+        return lab[:n]
+
+    def mlp_forward(self, model, x):
+        model = self._cuda_f32(model, PORDER_MODEL_FLOATS, "model")
+        x = self._cuda_f32(x, None, "x")
+        n = x.shape[0]
+        y = torch.empty(max(n, 1), dtype=torch.float32, device=x.device)
+        rc = self.lib.fmm2d_mlp_forward(self.h, _ptr(model), _ptr(x), n, _ptr(y), self._stream())
+        if rc != OK:
+            raise self._err(rc)
+        return y[:n]
+
+    def mlp_grad(self, model, x, q, tau: float, work=None):
+        """(grad [321], loss [1]) of the pinball loss, float32 CUDA."""
+        model = self._cuda_f32(model, PORDER_MODEL_FLOATS, "model")
+        x = self._cuda_f32(x, None, "x")
+        q = self._cuda_f32(q, x.shape[0], "q")
+        n = x.shape[0]
+        nbytes = int(self.lib.fmm2d_mlp_work_size(n))
+        if work is None or work.numel() < nbytes:
+            work = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        grad = torch.empty(PORDER_NPARAM, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        rc = self.lib.fmm2d_mlp_grad(self.h, _ptr(model), _ptr(x), _ptr(q), n, float(tau), _ptr(grad),
+                                     _ptr(loss), _ptr(work), work.numel(), self._stream())
+        if rc != OK:
+            raise self._err(rc)
+        return grad, loss
+
+    def mlp_adam(self, model, grad, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step on model's trainable parameters, in place."""
+        for t, nme in ((model, "model"), (grad, "grad"), (m, "m"), (v, "v")):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise TypeError("%s must be a contiguous float32 CUDA tensor" % nme)
+        rc = self.lib.fmm2d_mlp_adam(self.h, _ptr(model), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                                     float(beta1), float(beta2), float(eps), self._stream())
+        if rc != OK:
+            raise self._err(rc)
+
     def topology(self, coeffs: bool = False) -> dict:
         """Host (numpy) copies of the tree, lists (and coefficients) of the
         last evaluation, for the tests."""
@@ -292,6 +420,8 @@ class FMM2D:
             "weak_off": woff, "weak_idx": dev(tp.weak_idx, nw, np.int32),
             "strong_off": soff, "strong_idx": dev(tp.strong_idx, nsg, np.int32),
         }
+        if tp.porder:
+            out["porder"] = dev(tp.porder, nw, np.uint8)
         if coeffs:
             out["mpole"] = dev(tp.mpole, 2 * nb * (p + 1), np.float64).view(np.complex128).reshape(nb, p + 1)
             out["local"] = dev(tp.local, 2 * nb * (p + 1), np.float64).view(np.complex128).reshape(nb, p + 1)

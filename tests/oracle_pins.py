@@ -551,7 +551,287 @@ def pin_fmm_swap_converges(orc):
     assert last < 1e-8
 
 
+
+# ------------------------------------------------------- per-pair orders
+def pin_pair_err_point_source(orc):
+    """Closed forms of the truncation bound e_q for a point source at the
+    source centre.  Harmonic: a_1 = m only, so b_l = m (-1)^l rho^{-(l+1)}
+    exactly and truncation at q drops rows l > q:
+        e_q = |m| / |rho| sum_{l=q+1..P} (rT/|rho|)^l.
+    Log: a_0 = m only, b_l = -m (-w/rho)^l / l, so
+        e_q = |m| sum_{l=q+1..P} (rT/|rho|)^l / l."""
+    P, m, rho, rT = 24, 0.7 - 1.3j, 2.0 + 1.5j, 0.6
+    x = rT / abs(rho)
+    a = np.zeros(P + 1, complex)
+    a[1] = m
+    e = orc.pair_err(P, a, rho, rT, 0, P)
+    for q in range(1, P + 1):
+        ref = abs(m) / abs(rho) * sum(x ** l for l in range(q + 1, P + 1))
+        assert abs(e[q] - ref) <= 1e-13 * abs(m) / abs(rho), (q, e[q], ref)
+    a = np.zeros(P + 1, complex)
+    a[0] = m
+    e = orc.pair_err(P, a, rho, rT, 0, P)
+    for q in range(0, P + 1):
+        ref = abs(m) * sum(x ** l / l for l in range(q + 1, P + 1))
+        assert abs(e[q] - ref) <= 1e-13 * abs(m), (q, e[q], ref)
+
+
+def pin_pair_err_bounds_error(orc):
+    """e_q bounds the actual error of the truncated pair on the target disc:
+    for a cluster's multipole (order P), the local expansion of the pair
+    truncated at q differs from the one at P by at most e_q at every z with
+    |z - c_T| <= rT, and the bound is not loose by more than a few powers."""
+    P = 30
+    xs, ms = _cluster(3, n=25, c=0.0, rad=0.1)
+    cS, cT, rT = 0.0, 0.9 + 0.4j, 0.12
+    for kernel in (orc.KERNEL_HARMONIC, orc.KERNEL_LOG):
+        a = orc.p2m(kernel, P, cS, xs, ms)
+        bP = orc.m2l(P, a, cT - cS)
+        e = orc.pair_err(P, a, cT - cS, rT, 2, 20)
+        zs = cT + rT * np.exp(2j * np.pi * np.arange(64) / 64)
+        for q in range(2, 21):
+            bq = np.zeros(P + 1, complex)
+            bq[:q + 1] = orc.m2l(q, a[:q + 1], cT - cS)
+            err = max(abs(orc.eval_local(P, bq - bP, cT, z)[0]) for z in zs)
+            assert err <= e[q - 2] * (1 + 1e-9) + 1e-300, (kernel, q, err, e[q - 2])
+            assert err >= e[q - 2] * 1e-3, (kernel, q, err, e[q - 2])
+
+
+def pin_labels_budget(orc):
+    """Labels: the budget of box T is tol min_{y in T} |val(y)| / |weak(T)|
+    (recomputed here from the tree's targets and lists), and the label is the
+    smallest q in [qmin, qmax] with e_q <= budget (else qmax)."""
+    n = 3000
+    src = workloads.points("clusters", n, 21)
+    m = workloads.strengths(n, 22)
+    T = orc.Tree(src, 3)
+    P, tol, qmin, qmax = 24, 1e-6, 4, 20
+    _, dphi, A, _ = T.eval(m, P, orc.KERNEL_HARMONIC, want_coeffs=True)
+    lab, err, bud = T.labels(A, P, dphi, tol, qmin, qmax)
+    lv, tb, sb = T.weak_pairs()
+    assert lab.size == lv.size == T.n_weak() > 0
+    k = 0
+    for l in range(1, T.L + 1):
+        off, idx = T.weak[l]
+        st = T.starts(l, targets=True)
+        for b in range(4 ** l):
+            nw = int(off[b + 1] - off[b])
+            if nw == 0:
+                continue
+            tg = T.tperm[st[b]:st[b + 1]]
+            ref = tol * np.abs(dphi[tg]).min() / nw
+            for e in range(nw):
+                assert abs(bud[k] - ref) <= 4.5e-16 * ref, (l, b, bud[k], ref)
+                ok = np.nonzero(err[k] <= bud[k])[0]
+                want = qmin + ok[0] if ok.size else qmax
+                assert lab[k] == want
+                # e_q of the pair equals pair_err from the multipole directly
+                g, gs = orc.box_offset(l) + b, orc.box_offset(l) + int(idx[off[b] + e])
+                e2 = orc.pair_err(P, A[gs], T.centre[g] - T.centre[gs], T.radius[g], qmin, qmax)
+                assert np.array_equal(e2, err[k])
+                k += 1
+    assert k == lab.size
+
+
+def pin_orders_uniform(orc):
+    """Every pair at order q with storage p > q equals the plain FMM at p = q
+    (without the swapped criterion: P2M/M2M coefficients up to q do not depend
+    on p, the local expansions carry zeros above q).  Every pair at p equals
+    the plain FMM at p."""
+    n = 4000
+    src = workloads.points("clusters", n, 23)
+    m = workloads.strengths(n, 24)
+    T = orc.Tree(src, 3)
+    for kernel in (orc.KERNEL_HARMONIC, orc.KERNEL_LOG):
+        for q in (6, 11):
+            got = T.eval(m, 20, kernel, orders=np.full(T.n_weak(), q, np.uint8))
+            ref = T.eval(m, q, kernel)
+            assert _rel(got[1], ref[1]) < 1e-13
+            if kernel == orc.KERNEL_LOG:
+                assert _rel(got[0], ref[0]) < 1e-13
+        got = T.eval(m, 20, kernel, orders=np.full(T.n_weak(), 20, np.uint8))
+        ref = T.eval(m, 20, kernel)
+        assert np.array_equal(got[1], ref[1])
+
+
+def pin_orders_per_pair(orc):
+    """Per-pair orders reach the right pairs: the local expansions of a small
+    tree assembled here pair by pair (orc.m2l at each pair's order, then L2L
+    down the levels) equal the oracle's."""
+    n = 3000
+    src = workloads.points("clusters", n, 25)
+    m = workloads.strengths(n, 26)
+    T = orc.Tree(src, 3)
+    assert int(T.weak[2][0][-1]) > 0 and int(T.weak[3][0][-1]) > 0
+    p = 14
+    rng = np.random.default_rng(27)
+    q = rng.integers(1, p + 1, T.n_weak()).astype(np.uint8)
+    _, _, A, B = T.eval(m, p, orc.KERNEL_LOG, want_coeffs=True, orders=q)
+    Bref = np.zeros_like(B)
+    k = 0
+    for l in range(1, T.L + 1):
+        off, idx = T.weak[l]
+        for b in range(4 ** l):
+            g = orc.box_offset(l) + b
+            par = orc.box_offset(l - 1) + b // 4
+            if l > 1:
+                Bref[g] += orc.l2l(p, Bref[par], T.centre[g] - T.centre[par])
+            for e in range(off[b], off[b + 1]):
+                gs = orc.box_offset(l) + int(idx[e])
+                qq = int(q[k])
+                Bref[g, :qq + 1] += orc.m2l(qq, A[gs, :qq + 1], T.centre[g] - T.centre[gs])
+                k += 1
+    leaves = slice(orc.box_offset(T.L), orc.box_offset(T.L + 1))
+    assert k == q.size
+    assert _rel(B[leaves], Bref[leaves]) < 1e-13
+
+
+def pin_features_invariants(orc):
+    """The order features (oracle/porder.py): f2 = f0 + f1; the shares
+    10^f6 of one target box sum to 1; 10^f7 is the weak count; f3 = l/L;
+    f5 <= 0; and doubling every coordinate (exact in floating point) leaves
+    every feature unchanged (the coefficients are scaled by the box radii)."""
+    from oracle import porder
+    n = 4000
+    src = workloads.points("clusters", n, 28)
+    m = workloads.strengths(n, 29)
+    T = orc.Tree(src, 3)
+    p = 20
+    for kernel in (orc.KERNEL_HARMONIC, orc.KERNEL_LOG):
+        A = T.eval(m, p, kernel, want_coeffs=True)[2]
+        F = porder.features(T, A, p)
+        lv, tb, sb = T.weak_pairs()
+        assert np.allclose(F[:, 2], F[:, 0] + F[:, 1], rtol=1e-15, atol=0)
+        assert np.array_equal(F[:, 3], lv / T.L)
+        assert np.all(F[:, 5] <= 1e-15)
+        key = lv * 4 ** T.L + tb
+        share = np.zeros(key.max() + 1)
+        np.add.at(share, key, 10.0 ** F[:, 6])
+        cnt = np.bincount(key)
+        nz = cnt > 0
+        assert np.allclose(share[nz], 1.0, rtol=1e-13)
+        assert np.array_equal(np.rint(10.0 ** F[:, 7]).astype(int), cnt[key])
+        T2 = orc.Tree(2.0 * src, 3)
+        A2 = T2.eval(m, p, kernel, want_coeffs=True)[2]
+        F2 = porder.features(T2, A2, p)
+        assert np.allclose(F2, F, rtol=1e-12, atol=1e-12)
+    # the radius scaling matters: unscaled coefficients change under doubling
+    assert not np.allclose(np.abs(A2[1:, 3]) / np.abs(A[1:, 3]).clip(1e-300), 1.0)
+
+
+def _mlp_problem(seed, n=200):
+    from oracle import porder
+    rng = np.random.default_rng(seed)
+    w = np.zeros(porder.MODEL_FLOATS)
+    w[:porder.NPARAM] = rng.normal(0, 0.5, porder.NPARAM)
+    o = porder.NPARAM
+    w[o:o + 8] = rng.normal(0, 1, 8)               # mu
+    w[o + 8:o + 16] = rng.uniform(0.5, 2, 8)       # isd
+    w[o + 16:o + 24] = -1e30                       # lo
+    w[o + 24:o + 32] = 1e30                        # hi
+    F = rng.normal(0, 1, (n, 8))
+    q = rng.integers(4, 30, n).astype(float)
+    return w, F, q
+
+
+def pin_mlp_forward_by_hand(orc):
+    """A 2-unit network written out by hand: y = W2 . relu(W1 x + b1) + b2."""
+    from oracle import porder
+    w = np.zeros(porder.MODEL_FLOATS)
+    W1 = np.zeros((32, 8))
+    W1[0, 0], W1[0, 1], W1[1, 2] = 1.0, -2.0, 3.0
+    w[:256] = W1.ravel()
+    w[256:288][:2] = [0.5, -10.0]                  # b1
+    w[288:320][:2] = [2.0, 7.0]                    # W2
+    w[320] = 0.25                                  # b2
+    w[321:329] = 1.0                               # mu
+    w[329:337] = 0.5                               # isd
+    f = np.array([[3.0, 1.0, 5.0, 0, 0, 0, 0, 0], [1.0, 1.0, 30.0, 0, 0, 0, 0, 0]])
+    # x = (f - 1) / 2; unit 0: x0 - 2 x1 + 0.5; unit 1: 3 x2 - 10
+    # row 0: x = (1, 0, 2): z0 = 1.5, z1 = -4 -> y = 2 * 1.5 + 0.25 = 3.25
+    # row 1: x = (0, 0, 14.5): z0 = 0.5, z1 = 33.5 -> y = 1 + 234.5 + 0.25
+    y = porder.forward(w, f)
+    assert np.allclose(y, [3.25, 235.75], rtol=0, atol=1e-12), y
+
+
+def pin_mlp_gradient(orc):
+    """The hand-written back-propagation against central finite differences
+    of the loss (away from the kinks of the pinball loss and of relu), for two
+    quantiles."""
+    from oracle import porder
+    w, F, q = _mlp_problem(30)
+    for tau in (0.5, 0.9):
+        g = porder.grad(w, F, q, tau)
+        rng = np.random.default_rng(31)
+        for k in list(rng.choice(porder.NPARAM, 40, replace=False)) + [porder.NPARAM - 1, 256, 300]:
+            h = 1e-6
+            wp, wm = w.copy(), w.copy()
+            wp[k] += h
+            wm[k] -= h
+            fd = (porder.loss(wp, F, q, tau) - porder.loss(wm, F, q, tau)) / (2 * h)
+            assert abs(fd - g[k]) <= 1e-6 + 1e-5 * abs(fd), (tau, k, fd, g[k])
+
+
+def pin_pinball_quantile(orc):
+    """The pinball loss at quantile tau is minimised by the tau-quantile: for a
+    constant model (W1 = W2 = 0, y = b2) the derivative in b2 changes sign at
+    the empirical quantile of q; at tau = 1/2 the loss is half the mean
+    absolute deviation."""
+    from oracle import porder
+    rng = np.random.default_rng(32)
+    F = rng.normal(0, 1, (501, 8))
+    q = rng.normal(10, 3, 501)
+    w = np.zeros(porder.MODEL_FLOATS)
+    w[329:337] = 1.0
+    for tau in (0.1, 0.5, 0.98):
+        qs = np.sort(q)
+        k = int(np.ceil(tau * q.size)) - 1       # empirical tau-quantile
+        for b2, sign in ((qs[k] - 1e-6, -1), (qs[k] + 1e-6, 1)):
+            w[320] = b2
+            g = porder.grad(w, F, q, tau)[porder.NPARAM - 1]
+            assert np.sign(g) == sign, (tau, b2, g)
+    w[320] = 9.0
+    assert abs(porder.loss(w, F, q, 0.5) - 0.5 * np.mean(np.abs(q - 9.0))) < 1e-12
+
+
+def pin_adam_first_step(orc):
+    """Adam's first bias-corrected step moves every parameter by lr in the
+    direction opposite to the sign of its gradient (for |g| >> eps)."""
+    from oracle import porder
+    w, F, q = _mlp_problem(33)
+    g = porder.grad(w, F, q, 0.7)
+    big = np.abs(g) > 1e-4
+    w1, m1, v1 = porder.adam_step(w, g, np.zeros_like(g), np.zeros_like(g), 1, lr=0.01)
+    d = w1[:porder.NPARAM] - w[:porder.NPARAM]
+    assert np.allclose(d[big], -0.01 * np.sign(g[big]), rtol=1e-3)
+    assert np.array_equal(w1[porder.NPARAM:], w[porder.NPARAM:])
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+
+
+def pin_orders_decision(orc):
+    """The FP32 order decision: ceil(y + delta) clamped to [4, p], equal to the
+    FP64 forward pass except within 1e-4 of an integer; p wherever a feature
+    leaves [lo, hi]."""
+    from oracle import porder
+    w, F, q = _mlp_problem(34, n=2000)
+    w[:porder.NPARAM] *= 2.0
+    w[320] = 12.0
+    y64 = porder.forward(w, F) + 0.37
+    qq, yd = porder.orders(w, F, 0.37, 20)
+    ref = np.clip(np.ceil(y64), 4, 20)
+    far = np.abs(y64 - np.rint(y64)) > 1e-4
+    assert np.array_equal(qq[far], ref[far])
+    assert 4 in qq and 20 in qq and len(np.unique(qq)) > 8
+    w[porder.NPARAM + 16 + 3] = 0.5              # lo of feature 3
+    qq2, _ = porder.orders(w, F, 0.37, 20)
+    out = F[:, 3].astype(np.float32) < np.float32(0.5)
+    assert np.all(qq2[out] == 20) and np.array_equal(qq2[~out], qq[~out])
+
+
 ALL_PINS = [pin_level_rule, pin_direct_roots_of_unity, pin_direct_bruteforce, pin_p2m_far_field,
             pin_m2m_exact, pin_l2l_exact, pin_m2l_closed_forms, pin_m2l_convergence, pin_tree_hand,
             pin_tree_invariants, pin_tree_targets_on_pivot, pin_lists, pin_fmm_L0_is_direct,
-            pin_fmm_theta_small_is_direct, pin_fmm_converges, pin_fmm_lattice_ties, pin_p2l_near_field, pin_swap_lists, pin_fmm_swap_converges, pin_operating_point, pin_branch]
+            pin_fmm_theta_small_is_direct, pin_fmm_converges, pin_fmm_lattice_ties, pin_p2l_near_field, pin_swap_lists, pin_fmm_swap_converges, pin_operating_point, pin_branch,
+            pin_pair_err_point_source, pin_pair_err_bounds_error, pin_labels_budget, pin_orders_uniform,
+            pin_orders_per_pair, pin_features_invariants, pin_mlp_forward_by_hand, pin_mlp_gradient,
+            pin_pinball_quantile, pin_adam_first_step, pin_orders_decision]
