@@ -1,19 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the adaptive 2D FMM evaluation on one MI355X.
 
-One step = one full evaluation (tree build, lists, P2M, M2M, M2L, L2L, L2P,
-P2P, near+far sum) of Phi' for N = 2^22 sources drawn from 20 Gaussian
-clusters, evaluated at the sources, with inputs resident in HBM.  The headline
-path is the mixed-precision one (FP32 near field and FP32 M2L contraction);
-the plain FP64 path is timed beside it.  Each run's error is measured against
-a device FP64 direct sum on 10,000 seeded random targets.
+One step = one full evaluation (tree build, lists, P2M, M2M, order
+inference, M2L, L2L, P2L, near field with L2P and M2P, near + far sum) of
+Phi' for N = 2^22 sources drawn from 20 Gaussian clusters, evaluated at the
+sources, with inputs resident in HBM.  theta = 1/2, levels from eq.
+(Nlevels) with N_d = 45, storage order p = 20 (the a-priori order
+ceil(log 1e-6 / log theta)).
 
-Prints one JSON line (see the keys below).  `python bench.py --gpus N` with
-N > 1 exits: this build measures one GPU.
+Paths (each timed over the same K steps after W warm-up steps):
+  headline   FP32 M2L contraction (radius-scaled) + learned per-pair orders,
+             everything else FP64
+  fp64       the plain FP64 FMM at the fixed order p (the baseline)
+  far32      FP32 M2L contraction at the fixed order (ablation)
+  mixed      FP32 near field and FP32 M2L with learned orders (ablation)
+Each path's error is measured against the device FP64 direct sum at 10,000
+seeded sources (pointwise max |dPhi'|/|Phi'|, the TOL metric of Sec. 5.1).
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this measures one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,25 +32,44 @@ import numpy as np
 
 METRIC = "Mparticles/s, N=4M clustered, rel.err≤1e-6: mixed+learned-p vs plain FP64 FMM"
 WORKLOAD = "clusters4M"
-PEAK = {"f64": 78.6, "f32": 157.3}  # TFLOP/s, MI355X vector (FP32 figure assumes packed issue)
-HBM_PEAK = 8000.0  # GB/s
+TOL = 1e-6
+FP64_PEAK = 78.6    # TFLOP/s, MI355X FP64 vector
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_k_near_clusters4M.txt")
 
 
-def p2p_flops_per_pair(kernel: str) -> float:
-    """Algorithmic flops of one near-field pair (harmonic): w = y - x (2),
-    |w|^2 (3), 1/|w|^2 (1), m conj(w) (6), scale and accumulate (4)."""
-    return 16.0 if kernel == "harmonic" else 16.0 + 10.0
+def near_flops(st, n, p):
+    """Algorithmic flops of the near-field kernel (one launch): per P2P pair
+    16 (w = y - x: 2, |w|^2: 3, 1/|w|^2: 1, m conj(w): 6, scale: 2,
+    accumulate: 2); per target the L2P Horner sum, 8 flops per order; per M2P
+    evaluation the multipole Horner sum, 8 flops per order."""
+    return 16.0 * st["n_p2p_pairs"] + 8.0 * p * n + 8.0 * p * st["n_m2p_evals"]
 
 
-def l2p_flops_per_target(kernel: str, p: int) -> float:
-    """Horner evaluation of the local expansion: one complex multiply-add per
-    order (8 flops), twice with the derivative."""
-    return 8.0 * p * (1 if kernel == "harmonic" else 2)
+def traffic_bytes():
+    """HBM bytes per launch of the near-field kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source changed since
+    the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(HERE, "paper_1205_4611_amd", "csrc", "p2p.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("p2p.hip sha256[:16]") != sha:
+        return None
+    try:
+        return float(kv["hbm bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
-def run_path(f, fmm2d, src, m, kernel, p, precision, porder, steps, warmup):
+def run_path(f, fmm2d, src, m, p, precision, porder, steps, warmup):
     import torch
-    opts = fmm2d.make_opts(p=p, levels=-1, leaf_target=45, kernel=kernel, precision=precision,
+    opts = fmm2d.make_opts(p=p, levels=-1, leaf_target=45, kernel="harmonic", precision=precision,
                            porder=porder, timing=True, swap=True)
     out = None
     for _ in range(warmup):
@@ -51,32 +79,31 @@ def run_path(f, fmm2d, src, m, kernel, p, precision, porder, steps, warmup):
     t0 = time.perf_counter()
     for _ in range(steps):
         out = f.eval(src, m, opts=opts, check=False)
-        st = f.stats()  # synchronises; per-phase device times from HIP events on the eval stream
-        for k, v in st["ms"].items():
+        for k, v in f.times().items():  # HIP events on the evaluation's stream
             phases[k] += v
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    f.sync()
+    st = f.stats()
     ms = (t1 - t0) * 1e3 / steps
-    phases = {k: v / steps for k, v in phases.items()}
-    return out, ms, phases, st
+    return out, ms, {k: v / steps for k, v in phases.items()}, st
 
 
-def errors(f, src, m, dphi, sel, kernel):
+def errors(f, src, m, dphi, sel):
     """Pointwise and normwise relative error of Phi' against the device FP64
     direct sum at the selected targets."""
     import torch
     _, ref = f.direct(src, m, tsel=sel, kernel="harmonic")
-    got = dphi[sel]
-    e = (got - ref).abs()
-    pt = (e / ref.abs()).max().item()
-    nrm = (e.max() / ref.abs().max()).item()
-    q = torch.quantile((e / ref.abs()).float(), 0.999).item()
-    return {"pt": pt, "nrm": nrm, "pt_q999": q}
+    e = (dphi[sel] - ref).abs()
+    r = e / ref.abs()
+    return {"pt": r.max().item(), "nrm": (e.max() / ref.abs().max()).item(),
+            "pt_q999": torch.quantile(r.float(), 0.999).item()}
 
 
 def cpu_baseline(n_sample: int, p: int):
-    """The oracle (plain C, FP64, OpenMP over all host cores) on a bounded
-    sample of the same workload: the same distribution at n_sample points."""
+    """The oracle (plain C, FP64, OpenMP over the host cores) on a bounded
+    sample of the same workload: the same distribution at n_sample points,
+    tree + lists + evaluation with the swapped leaf criterion."""
     import oracle
     from paper_1205_4611_amd import workloads
     oracle.build()
@@ -85,13 +112,24 @@ def cpu_baseline(n_sample: int, p: int):
     m = workloads.strengths(n_sample, w["mseed"])
     L = oracle.nlevels(n_sample, 45)
     t0 = time.perf_counter()
-    T = oracle.Tree(src, L)
+    T = oracle.Tree(src, L, swap=True)
     T.eval(m, p, oracle.KERNEL_HARMONIC)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count()
     return {"value": n_sample / dt / 1e6, "unit": "Mparticles/s", "cores": cores, "kind": "oracle",
-            "sample": "oracle FMM (tree+lists+eval, p=%d, harmonic) on %d points of the same 20-cluster "
-                      "distribution, %.1f s wall" % (p, n_sample, dt)}
+            "sample": "oracle FMM (tree, lists, evaluation; FP64, p=%d, harmonic, fixed order) on %d points "
+                      "of the same 20-cluster distribution: %.1f s wall" % (p, n_sample, dt)}
+
+
+def copy_calibration(nbytes: int, reps: int):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
 def main():
@@ -100,44 +138,53 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=0, help="override N (default 2^22)")
-    ap.add_argument("--p", type=int, default=17)
-    ap.add_argument("--kernel", default="harmonic", choices=["harmonic", "log"])
+    ap.add_argument("--p", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--paths", default="headline,fp64,far32,mixed")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU path is not part of this build "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, 5)
+        return
 
     import torch
     from paper_1205_4611_amd import fmm2d, workloads
 
     w = workloads.WORKLOADS[WORKLOAD]
     n = args.n or w["n"]
-    src_h = workloads.points(w["dist"], n, w["seed"])
-    m_h = workloads.strengths(n, w["mseed"])
-    sel_h = workloads.sample_indices(n, 10_000, w["sel_seed"])
-    src = torch.from_numpy(src_h).cuda()
-    m = torch.from_numpy(m_h).cuda()
-    sel = torch.from_numpy(sel_h).cuda()
+    src = torch.from_numpy(workloads.points(w["dist"], n, w["seed"])).cuda()
+    m = torch.from_numpy(workloads.strengths(n, w["mseed"])).cuda()
+    sel = torch.from_numpy(workloads.sample_indices(n, 10_000, w["sel_seed"])).cuda()
     f = fmm2d.FMM2D(0)
+    model, delta, meta = fmm2d.load_porder_model()
+    f.set_porder_model(model, delta)
 
+    spec = {"headline": ("mixed_far", "learned"), "fp64": ("fp64", "fixed"),
+            "far32": ("mixed_far", "fixed"), "mixed": ("mixed", "learned")}
+    names = [x for x in args.paths.split(",") if x]
+    if "headline" not in names or "fp64" not in names:
+        raise SystemExit("--paths must include headline and fp64")
     res = {}
-    for name, prec, porder in (("fp64", "fp64", "fixed"), ("mixed", "mixed", "fixed")):
-        out, ms, ph, st = run_path(f, fmm2d, src, m, args.kernel, args.p, prec, porder, args.steps, args.warmup)
-        err = errors(f, src, m, out[1], sel, args.kernel)
-        res[name] = dict(ms=ms, phases=ph, stats=st, err=err)
+    for name in names:
+        prec, porder = spec[name]
+        out, ms, ph, st = run_path(f, fmm2d, src, m, args.p, prec, porder, args.steps, args.warmup)
+        hist = np.array(st["p_hist"][:args.p + 1], np.float64)
+        res[name] = dict(ms=ms, phases=ph, stats=st, err=errors(f, src, m, out[1], sel),
+                         mean_order=float((hist * np.arange(args.p + 1)).sum() / max(hist.sum(), 1)),
+                         used_model=st["used_model"])
 
-    head = res["mixed"]
+    head, base = res["headline"], res["fp64"]
     st = head["stats"]
     L = fmm2d.nlevels(n, 45)
-    pairs = st["n_p2p_pairs"]
-    flops = pairs * p2p_flops_per_pair(args.kernel) + n * l2p_flops_per_target(args.kernel, args.p)
+    flops = near_flops(st, n, args.p)
     p2p_ms = head["phases"]["p2p"]
     achieved = flops / (p2p_ms * 1e-3) / 1e12
-    fp64 = res["fp64"]
-    a64 = flops / (fp64["phases"]["p2p"] * 1e-3) / 1e12
     line = {
         "metric": METRIC,
         "value": n / (head["ms"] * 1e-3) / 1e6,
@@ -149,24 +196,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": "%s: N=%d sources, 20 Gaussian clusters, Phi' at the sources" % (WORKLOAD, n),
-                   "kernel": args.kernel, "theta": 0.5, "p": args.p, "levels": L, "leaf_target": 45,
-                   "path": "mixed (FP32 P2P + FP32 MFMA M2L), fixed p"},
+                   "kernel": "harmonic", "theta": 0.5, "p": args.p, "levels": L, "leaf_target": 45,
+                   "path": "FP32 M2L contraction + learned per-pair orders, FP64 elsewhere",
+                   "porder_model": os.path.basename(fmm2d.MODEL_PATH), "delta": delta},
         "err": head["err"],
-        "fp64": {"value": n / (fp64["ms"] * 1e-3) / 1e6, "ms_per_step": fp64["ms"], "err": fp64["err"],
-                 "phases_ms": fp64["phases"],
-                 "p2p_roofline": {"bound": "alu", "achieved": a64, "peak": PEAK["f64"], "unit": "TFLOP/s",
-                                  "frac": a64 / PEAK["f64"]}},
-        "speedup_vs_fp64": fp64["ms"] / head["ms"],
+        "meets_tol": head["err"]["pt"] <= TOL,
+        "mean_order": head["mean_order"],
+        "speedup_vs_fp64": base["ms"] / head["ms"],
         "phases_ms": head["phases"],
         "counts": {"m2l_pairs": st["n_weak"], "p2p_leaf_pairs": st["n_strong"], "m2p_leaf_pairs": st["n_m2p"],
-                   "p2l_leaf_pairs": st["n_p2l"], "p2p_pairs": pairs},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f32"], "traffic": None,
-                     "kernel": "k_p2p32 (near field + L2P)",
-                     "flops_per_launch": flops},
+                   "p2l_leaf_pairs": st["n_p2l"], "p2p_pairs": st["n_p2p_pairs"],
+                   "m2p_evals": st["n_m2p_evals"], "p2l_evals": st["n_p2l_evals"]},
+        "paths": {k: {"value": n / (v["ms"] * 1e-3) / 1e6, "ms_per_step": v["ms"], "err": v["err"],
+                      "mean_order": v["mean_order"], "used_model": v["used_model"],
+                      "phases_ms": v["phases"]} for k, v in res.items() if k != "headline"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK, "traffic": traffic_bytes(),
+                     "kernel": "k_near (P2P + L2P + M2P, FP64)", "flops_per_launch": flops,
+                     "avg_launch_ms": p2p_ms},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.p)

@@ -201,11 +201,18 @@ typedef struct fmm2d_stats {
     int64_t n_m2p;       /* M2P leaf pairs */
     int64_t n_p2l;       /* P2L leaf pairs */
     int64_t n_p2p_pairs; /* point-point pair evaluations in P2P */
+    int64_t n_m2p_evals; /* multipole evaluations at targets (M2P) */
+    int64_t n_p2l_evals; /* source contributions to local expansions (P2L) */
     int32_t status;      /* as fmm2d_sync */
     int32_t used_model;  /* 1 if the learned order model was used */
     int64_t p_hist[65];  /* M2L pairs per order q = 0..64 (all at p when fixed) */
 } fmm2d_stats;
 int fmm2d_get_stats(fmm2d_handle *h, fmm2d_stats *out);
+
+/* Per-phase device times of the last evaluation only (ms[FMM2D_NPHASE],
+ * host array; -1 without FMM2D_FLAG_TIMING).  Waits for the last phase's
+ * event, copies nothing else: cheap enough to call after every evaluation. */
+int fmm2d_get_times(fmm2d_handle *h, float *ms);
 
 /* ---- per-interaction truncation order ----------------------------------
  * The method uses one order p for all M2L interactions (the a-priori rule

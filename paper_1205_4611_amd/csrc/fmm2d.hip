@@ -494,6 +494,24 @@ extern "C" int fmm2d_get_stats(fmm2d_handle *h, fmm2d_stats *s)
             }
             s->n_p2p_pairs = pairs;
         }
+        // M2P evaluations (targets x source leaves) and P2L contributions
+        // (sources of the P2L leaves, per target leaf)
+        int32_t *mo = (int32_t *)malloc(4 * (nl + 1));
+        int32_t *po = (int32_t *)malloc(4 * (nl + 1));
+        int32_t *pi = (int32_t *)malloc(4 * (s->n_p2l + 1));
+        if (e == hipSuccess) e = hipMemcpy(mo, w + lay.moff, 4 * (nl + 1), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(po, w + lay.poff, 4 * (nl + 1), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && s->n_p2l > 0) e = hipMemcpy(pi, w + lay.pidx, 4 * s->n_p2l, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) {
+            int64_t me = 0, pe = 0;
+            for (int64_t t = 0; t < nl; ++t) {
+                me += (int64_t)(mo[t + 1] - mo[t]) * (ts[t + 1] - ts[t]);
+                for (int32_t k = po[t]; k < po[t + 1]; ++k) pe += ss[pi[k] + 1] - ss[pi[k]];
+            }
+            s->n_m2p_evals = me;
+            s->n_p2l_evals = pe;
+        }
+        free(mo); free(po); free(pi);
         free(so); free(ss); free(ts); free(si);
         HIPCHK(h, e);
     }
@@ -508,6 +526,18 @@ extern "C" int fmm2d_get_stats(fmm2d_handle *h, fmm2d_stats *s)
     } else {
         s->p_hist[h->p] = s->n_weak;
     }
+    return FMM2D_OK;
+}
+
+extern "C" int fmm2d_get_times(fmm2d_handle *h, float *ms)
+{
+    if (!h || !ms) return FMM2D_EINVAL;
+    for (int i = 0; i < FMM2D_NPHASE; ++i) ms[i] = -1.0f;
+    if (!h->have_topo) return fail(h, FMM2D_EINVAL, "no evaluation yet");
+    if (!h->timing_valid) return FMM2D_OK;
+    HIPCHK(h, hipSetDevice(h->device));
+    HIPCHK(h, hipEventSynchronize(h->ev[FMM2D_NPHASE]));
+    for (int i = 0; i < FMM2D_NPHASE; ++i) HIPCHK(h, hipEventElapsedTime(&ms[i], h->ev[i], h->ev[i + 1]));
     return FMM2D_OK;
 }
 

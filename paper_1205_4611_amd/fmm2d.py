@@ -36,7 +36,7 @@ PORDER_QMIN = 4
 #: every symbol include/fmm2d.h declares
 EXPORTS = ("fmm2d_default_opts", "fmm2d_create", "fmm2d_destroy", "fmm2d_last_error",
            "fmm2d_nlevels", "fmm2d_workspace_size", "fmm2d_eval", "fmm2d_direct",
-           "fmm2d_sync", "fmm2d_get_topology", "fmm2d_get_stats",
+           "fmm2d_sync", "fmm2d_get_topology", "fmm2d_get_stats", "fmm2d_get_times",
            "fmm2d_set_porder_model", "fmm2d_set_pair_orders", "fmm2d_pair_features",
            "fmm2d_pair_labels", "fmm2d_mlp_work_size", "fmm2d_mlp_forward", "fmm2d_mlp_grad",
            "fmm2d_mlp_adam")
@@ -62,9 +62,28 @@ class Topology(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_float * 9), ("n_weak", ctypes.c_int64),
                 ("n_strong", ctypes.c_int64), ("n_m2p", ctypes.c_int64), ("n_p2l", ctypes.c_int64),
-                ("n_p2p_pairs", ctypes.c_int64),
+                ("n_p2p_pairs", ctypes.c_int64), ("n_m2p_evals", ctypes.c_int64),
+                ("n_p2l_evals", ctypes.c_int64),
                 ("status", ctypes.c_int32), ("used_model", ctypes.c_int32),
                 ("p_hist", ctypes.c_int64 * 65)]
+
+
+MODEL_PATH = os.path.join(_HERE, "porder_model.json")
+
+
+def load_porder_model(path: str = MODEL_PATH):
+    """(model float32[353], delta, metadata) from a JSON file written by
+    train_porder.py."""
+    import json
+    import numpy as np
+    with open(path) as fh:
+        d = json.load(fh)
+    if int(d.get("schema", -1)) != PORDER_SCHEMA:
+        raise ValueError("%s: unknown feature schema %r" % (path, d.get("schema")))
+    w = np.asarray(d["model"], dtype=np.float32)
+    if w.size != PORDER_MODEL_FLOATS:
+        raise ValueError("%s: model has %d floats, expected %d" % (path, w.size, PORDER_MODEL_FLOATS))
+    return w, float(d["delta"]), d
 
 
 _lib = None
@@ -103,6 +122,8 @@ def load():
     lib.fmm2d_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.fmm2d_get_stats.restype = ctypes.c_int
     f32 = ctypes.c_float
+    lib.fmm2d_get_times.argtypes = [P, P]
+    lib.fmm2d_get_times.restype = ctypes.c_int
     lib.fmm2d_set_porder_model.argtypes = [P, P, i64, u32, f32]
     lib.fmm2d_set_porder_model.restype = ctypes.c_int
     lib.fmm2d_set_pair_orders.argtypes = [P, P, i64]
@@ -276,7 +297,8 @@ class FMM2D:
             raise self._err(rc)
         return {"ms": {k: float(st.ms[i]) for i, k in enumerate(PHASES)}, "n_weak": st.n_weak,
                 "n_strong": st.n_strong, "n_m2p": st.n_m2p, "n_p2l": st.n_p2l,
-                "n_p2p_pairs": st.n_p2p_pairs, "status": st.status,
+                "n_p2p_pairs": st.n_p2p_pairs, "n_m2p_evals": st.n_m2p_evals,
+                "n_p2l_evals": st.n_p2l_evals, "status": st.status,
                 "used_model": st.used_model, "p_hist": list(st.p_hist)}
 
     # ---- per-interaction orders -------------------------------------------
@@ -377,6 +399,15 @@ class FMM2D:
                                      float(beta1), float(beta2), float(eps), self._stream())
         if rc != OK:
             raise self._err(rc)
+
+    def times(self) -> dict:
+        """Per-phase device milliseconds of the last evaluation (needs
+        timing=True in its options); waits for it, copies nothing else."""
+        ms = (ctypes.c_float * len(PHASES))()
+        rc = self.lib.fmm2d_get_times(self.h, ms)
+        if rc != OK:
+            raise self._err(rc)
+        return {k: float(ms[i]) for i, k in enumerate(PHASES)}
 
     def topology(self, coeffs: bool = False) -> dict:
         """Host (numpy) copies of the tree, lists (and coefficients) of the

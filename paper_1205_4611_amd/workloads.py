@@ -107,6 +107,18 @@ def sample_indices(n: int, k: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
 
 
+def pair_orders(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """n truncation orders drawn uniformly from [lo, hi] (uint8), for tests of
+    per-pair M2L orders."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(lo, hi + 1, size=n).astype(np.uint8)
+
+
+# Training and validation draws of the learned order model: independent
+# 2^20-point draws of the 20-cluster distribution (strength seed = seed + 100).
+PORDER_TRAIN_SEEDS = (11, 12, 13, 14)
+PORDER_VAL_SEED = 15
+
 # The measured workloads: (name, sources, separate targets or None, seeds).
 WORKLOADS = {
     "uniform10k": dict(dist="uniform", n=10_000, seed=1, mseed=101, nd=40, tgt=None),

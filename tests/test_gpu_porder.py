@@ -1,0 +1,300 @@
+"""Per-pair M2L orders on the GPU against the oracle (through the C ABI).
+
+Given orders: the whole FMM at one order per weak pair equals the oracle's
+(<= 1e-12 normwise in FP64).  Features: FP32 from FP64 quantities, to FP32
+rounding.  Labels: integers decided by FP64 comparisons on both sides; they
+agree except where the oracle's e_q lies within 1e-6 (relative) of the
+budget.  MLP forward, gradient and Adam: FP32 against the FP64 oracle (1e-4
+relative).  Learned orders: the FP32 decision ceil(y + delta) agrees with the
+oracle's FP32 decision; delta is placed (from the oracle's values only) away
+from integer boundaries, so the orders agree exactly and the FMM matches the
+oracle's.
+"""
+import numpy as np
+import pytest
+
+from paper_1205_4611_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(z):
+    return None if z is None else torch.from_numpy(np.ascontiguousarray(z, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def nrm(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1205_4611_amd import fmm2d
+    f = fmm2d.FMM2D(0)
+    yield f
+    f.close()
+
+
+CASES = {
+    # name: (dist, n, L, targets (dist, n, seed) or None, seed)
+    "clusters20k": ("clusters", 20_000, 5, None, 81),
+    "gauss10_targets": ("gauss10", 6_000, 3, ("gauss10", 4_000, 82), 83),
+    "spiral_ragged": ("spiral", 10_007, 4, None, 84),
+}
+
+
+def _case(name):
+    dist, n, L, tspec, seed = CASES[name]
+    src = workloads.points(dist, n, seed)
+    tgt = None if tspec is None else workloads.points(*tspec)
+    m = workloads.strengths(n, seed + 100)
+    return src, m, tgt, L
+
+
+@pytest.mark.parametrize("kernel", ["log", "harmonic"])
+@pytest.mark.parametrize("name,p,swap", [("clusters20k", 20, False), ("gauss10_targets", 17, True),
+                                         ("spiral_ragged", 24, True), ("clusters20k", 40, False)])
+def test_given_orders_match_oracle(fmm, orc, name, p, swap, kernel):
+    src, m, tgt, L = _case(name)
+    T = orc.Tree(src, L, tgt=tgt, swap=swap)
+    q = workloads.pair_orders(T.n_weak(), 1, p, 85)
+    k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
+    rp, rd = T.eval(m, p, k, orders=q)
+    qd = torch.from_numpy(q).cuda()
+    fmm.set_pair_orders(qd)
+    gp, gd = fmm.eval(dev(src), dev(m), dev(tgt), p=p, levels=L, kernel=kernel, swap=swap, porder="given")
+    top = fmm.topology()
+    assert np.array_equal(top["porder"], q)
+    st = fmm.stats()
+    assert st["p_hist"][:p + 1] == list(np.bincount(q, minlength=p + 1)) and st["used_model"] == 0
+    assert nrm(host(gd), rd) < 1e-12
+    if kernel == "log":
+        assert nrm(host(gp), rp) < 1e-12
+    # FP32 contraction with the same orders (far-field-only mixed precision)
+    _, gd32 = fmm.eval(dev(src), dev(m), dev(tgt), p=p, levels=L, kernel=kernel, swap=swap, porder="given",
+                       precision="mixed_far")
+    assert nrm(host(gd32), rd) < 2e-6
+    fmm.set_pair_orders(None)
+
+
+def test_given_orders_too_few(fmm):
+    src, m, tgt, L = _case("clusters20k")
+    fmm.set_pair_orders(torch.full((10,), 5, dtype=torch.uint8, device="cuda"))
+    from paper_1205_4611_amd import fmm2d
+    with pytest.raises(fmm2d.FMMError) as e:
+        fmm.eval(dev(src), dev(m), p=20, levels=L, kernel="harmonic", porder="given")
+    assert e.value.code == fmm2d.EINVAL
+    fmm.set_pair_orders(None)
+    with pytest.raises(fmm2d.FMMError):
+        fmm.eval(dev(src), dev(m), p=20, levels=L, kernel="harmonic", porder="given")
+
+
+@pytest.mark.parametrize("kernel", ["log", "harmonic"])
+def test_features_match_oracle(fmm, orc, kernel):
+    from oracle import porder
+    src, m, tgt, L = _case("clusters20k")
+    p = 22
+    fmm.eval(dev(src), dev(m), p=p, levels=L, kernel=kernel)
+    F = fmm.pair_features().cpu().numpy()
+    T = orc.Tree(src, L)
+    k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
+    A = T.eval(m, p, k, want_coeffs=True)[2]
+    Fo = porder.features(T, A, p)
+    assert F.shape == Fo.shape and F.shape[0] == T.n_weak()
+    tol = 4 * 2.0 ** -24 * np.maximum(np.abs(Fo), 1.0) + 1e-6
+    bad = np.abs(F - Fo) > tol
+    assert not bad.any(), (np.argwhere(bad)[:5], F[bad][:5], Fo[bad][:5])
+
+
+@pytest.mark.parametrize("kernel", ["log", "harmonic"])
+def test_labels_match_oracle(fmm, orc, kernel):
+    src, m, tgt, L = _case("clusters20k")
+    P, tol, qmin, qmax = 36, 1e-6, 4, 30
+    gp, gd = fmm.eval(dev(src), dev(m), p=P, levels=L, kernel=kernel)
+    val = gp if kernel == "log" else gd
+    lab = fmm.pair_labels(val, tol, qmin, qmax).cpu().numpy()
+    T = orc.Tree(src, L)
+    k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
+    rp, rd, A, _ = T.eval(m, P, k, want_coeffs=True)
+    lo, err, bud = T.labels(A, P, rp if kernel == "log" else rd, tol, qmin, qmax)
+    assert lab.shape == lo.shape
+    mis = np.nonzero(lab != lo)[0]
+    assert mis.size <= max(3, lo.size // 1000), mis.size
+    for i in mis:
+        # a near-tie: the oracle's error bound at the smaller of the two labels
+        # sits on the budget
+        qq = min(int(lab[i]), int(lo[i])) - qmin
+        assert abs(err[i, qq] - bud[i]) <= 1e-6 * bud[i], (i, lab[i], lo[i], err[i, qq], bud[i])
+    assert len(np.unique(lo)) > 5
+
+
+def _random_model(seed, n=3000, scale=1.0):
+    from oracle import porder
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = np.zeros(porder.MODEL_FLOATS)
+    w[:porder.NPARAM] = rng.normal(0, 0.4 * scale, porder.NPARAM)
+    o = porder.NPARAM
+    w[o:o + 8] = rng.normal(0, 1, 8)
+    w[o + 8:o + 16] = rng.uniform(0.5, 2, 8)
+    w[o + 16:o + 24] = -1e30
+    w[o + 24:o + 32] = 1e30
+    F = rng.normal(0, 1, (n, 8))
+    q = rng.integers(4, 31, n).astype(np.float64)
+    return w, F, q
+
+
+def _f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("n", [1, 255, 3000])
+def test_mlp_forward_and_gradient(fmm, n):
+    from oracle import porder
+    w, F, q = _random_model(86, n)
+    # the oracle runs on the FP32-rounded parameters and inputs
+    w32 = w.astype(np.float32).astype(np.float64)
+    F32 = F.astype(np.float32).astype(np.float64)
+    y = fmm.mlp_forward(_f32(w), _f32(F)).cpu().numpy()
+    yo = porder.forward(w32, F32)
+    assert np.max(np.abs(y - yo)) <= 1e-4 * max(1.0, np.max(np.abs(yo)))
+    for tau in (0.5, 0.95):
+        g, loss = fmm.mlp_grad(_f32(w), _f32(F), _f32(q), tau)
+        g = g.cpu().numpy()
+        go = porder.grad(w32, F32, q, tau)
+        assert np.max(np.abs(g - go)) <= 1e-4 * np.max(np.abs(go)), (tau, np.max(np.abs(g - go)))
+        assert abs(loss.item() - porder.loss(w32, F32, q, tau)) <= 1e-4 * porder.loss(w32, F32, q, tau)
+
+
+def test_mlp_adam(fmm):
+    from oracle import porder
+    w, F, q = _random_model(87)
+    w32 = w.astype(np.float32).astype(np.float64)
+    g = porder.grad(w32, F.astype(np.float32).astype(np.float64), q, 0.9)
+    m = np.zeros(porder.NPARAM)
+    v = np.zeros(porder.NPARAM)
+    wd, gd, md, vd = _f32(w), _f32(g), _f32(m), _f32(v)
+    wo = w32
+    for step in (1, 2, 3):
+        fmm.mlp_adam(wd, gd, md, vd, step, lr=0.01)
+        wo, m, v = porder.adam_step(wo, g.astype(np.float32).astype(np.float64), m, v, step, lr=0.01)
+    got = wd.cpu().numpy()
+    assert np.max(np.abs(got - wo)) <= 1e-5 * max(1.0, np.max(np.abs(wo)))
+    assert np.array_equal(got[porder.NPARAM:], w.astype(np.float32)[porder.NPARAM:])
+
+
+def test_mlp_training_reduces_loss(fmm):
+    """A few hundred GPU Adam steps on a quantile target lower the pinball loss
+    (the oracle's FP64 loss of the trained weights)."""
+    from oracle import porder
+    rng = np.random.Generator(np.random.PCG64(88))
+    F = rng.normal(0, 1, (4000, 8))
+    q = np.rint(12 + 3 * F[:, 0] - 2 * np.maximum(F[:, 1], 0) + rng.normal(0, 0.5, 4000))
+    w, _, _ = _random_model(89, 1, scale=0.5)
+    w[porder.NPARAM:porder.NPARAM + 8] = 0.0
+    w[porder.NPARAM + 8:porder.NPARAM + 16] = 1.0
+    wd, Fd, qd = _f32(w), _f32(F), _f32(q)
+    md = torch.zeros(porder.NPARAM, dtype=torch.float32, device="cuda")
+    vd = torch.zeros_like(md)
+    l0 = porder.loss(w.astype(np.float32).astype(np.float64), F, q, 0.9)
+    for step in range(1, 301):
+        g, _ = fmm.mlp_grad(wd, Fd, qd, 0.9)
+        fmm.mlp_adam(wd, g, md, vd, step, lr=0.02)
+    l1 = porder.loss(wd.cpu().numpy().astype(np.float64), F, q, 0.9)
+    assert l1 < 0.3 * l0, (l0, l1)
+
+
+def _range_bounds(w, Fo):
+    """Training range in the model: the middle of the features, so that some
+    pairs fall outside.  Each bound is the midpoint of the widest gap between
+    distinct feature values near the 2% / 98% points, so no value sits within
+    FP32 rounding of a bound."""
+    from oracle import porder
+    o = porder.NPARAM
+    for i in range(8):
+        u = np.unique(Fo[:, i])
+        for side, (a, b) in ((16, (0.01, 0.05)), (24, (0.95, 0.99))):
+            if u.size < 2:
+                w[o + side + i] = u[0] - 1 if side == 16 else u[0] + 1
+                continue
+            j0 = int(a * (u.size - 1))
+            j1 = min(max(int(b * (u.size - 1)), j0 + 1), u.size - 1)
+            j = j0 + int(np.argmax(np.diff(u[j0:j1 + 1])))
+            w[o + side + i] = 0.5 * (u[j] + u[j + 1])
+
+
+@pytest.mark.parametrize("kernel", ["log", "harmonic"])
+@pytest.mark.parametrize("name,swap", [("clusters20k", False), ("gauss10_targets", True)])
+def test_learned_orders_match_oracle(fmm, orc, name, swap, kernel):
+    from oracle import porder
+    src, m, tgt, L = _case(name)
+    p = 22
+    k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
+    T = orc.Tree(src, L, tgt=tgt, swap=swap)
+    A = T.eval(m, p, k, want_coeffs=True)[2]
+    Fo = porder.features(T, A, p)
+    o = porder.NPARAM
+    # (1) a full random model: the orders agree except at near-ties of the
+    # FP32 decision (|y + delta - integer| < 1e-4 on the oracle side)
+    w, _, _ = _random_model(90, 1)
+    w[o:o + 8] = Fo.mean(axis=0)
+    w[o + 8:o + 16] = 1.0 / np.maximum(Fo.std(axis=0), 1e-3)
+    w[320] = 12.0
+    _range_bounds(w, Fo)
+    qo, yd = porder.orders(w, Fo, 0.25, p)
+    assert 0 < np.sum(qo == p) < qo.size and len(np.unique(qo)) > 5
+    fmm.set_porder_model(w.astype(np.float32), 0.25)
+    fmm.eval(dev(src), dev(m), dev(tgt), p=p, levels=L, kernel=kernel, swap=swap, porder="learned")
+    assert fmm.stats()["used_model"] == 1
+    qg = fmm.topology()["porder"]
+    mis = np.nonzero(qg != qo)[0]
+    tie = np.abs(yd - np.rint(yd)) < 1e-4
+    assert np.all(tie[mis]) and mis.size <= max(2, qo.size // 1000), mis.size
+    # (2) a model of the discrete features only (level, weak count): its
+    # outputs take few values, delta keeps them away from integers, the
+    # orders agree exactly and the FMM matches the oracle's at those orders
+    w2 = w.copy()
+    W1 = w2[:256].reshape(32, 8)
+    W1[:, [0, 1, 2, 4, 5, 6]] = 0.0
+    w2[:256] = W1.ravel()
+    w2[288:320] *= 4.0
+    _, y0 = porder.orders(w2, Fo, 0.0, p)
+    cand = np.linspace(0, 1, 401)[:-1]
+    dist = [np.min(np.abs((y0 + c) - np.rint(y0 + c))) for c in cand]
+    delta = float(np.float32(cand[int(np.argmax(dist))]))
+    assert max(dist) > 1e-3
+    qo, _ = porder.orders(w2, Fo, delta, p)
+    assert 0 < np.sum(qo == p) < qo.size and len(np.unique(qo)) > 3
+    fmm.set_porder_model(w2.astype(np.float32), delta)
+    gp, gd = fmm.eval(dev(src), dev(m), dev(tgt), p=p, levels=L, kernel=kernel, swap=swap, porder="learned")
+    st = fmm.stats()
+    assert st["used_model"] == 1
+    assert np.array_equal(fmm.topology()["porder"], qo)
+    assert st["p_hist"][:p + 1] == list(np.bincount(qo, minlength=p + 1))
+    rp, rd = T.eval(m, p, k, orders=qo)
+    assert nrm(host(gd), rd) < 1e-12
+    if kernel == "log":
+        assert nrm(host(gp), rp) < 1e-12
+    fmm.set_porder_model(None)
+
+
+def test_learned_without_model_is_fixed(fmm):
+    src, m, tgt, L = _case("clusters20k")
+    fmm.set_porder_model(None)
+    _, ref = fmm.eval(dev(src), dev(m), p=20, levels=L, kernel="harmonic")
+    _, got = fmm.eval(dev(src), dev(m), p=20, levels=L, kernel="harmonic", porder="learned")
+    st = fmm.stats()
+    assert st["used_model"] == 0 and st["p_hist"][20] == st["n_weak"]
+    assert torch.equal(got, ref)
+    from paper_1205_4611_amd import fmm2d
+    with pytest.raises(fmm2d.FMMError) as e:
+        fmm.eval(dev(src), dev(m), p=20, levels=L, kernel="harmonic", porder="learned", require_model=True)
+    assert e.value.code == fmm2d.ENOMODEL
+    with pytest.raises(fmm2d.FMMError):
+        fmm.set_porder_model(np.zeros(10, np.float32))
