@@ -39,6 +39,57 @@ __device__ __forceinline__ double2 cinv(double2 a)
     return make_double2(a.x * q, -a.y * q);
 }
 
+// 1/x from the hardware reciprocal and one Newton step (relative error
+// ~1e-15, against ~5e-8 for the bare instruction); x > 0 finite.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double2 cinv_fast(double2 a)
+{
+    const double q = rcp_nr(a.x * a.x + a.y * a.y);
+    return make_double2(a.x * q, -a.y * q);
+}
+
+// Cross-lane moves inside a row of 16 lanes through DPP (no LDS traffic).
+// DPP_XOR1: lanes 2i <-> 2i+1 (quad_perm 1,0,3,2); DPP_XOR2: quad_perm
+// 2,3,0,1; DPP_ROR4 / DPP_ROR8: rotate the row right by 4 / 8 lanes.
+#define DPP_XOR1 0xB1
+#define DPP_XOR2 0x4E
+#define DPP_ROR4 0x124
+#define DPP_ROR8 0x128
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// Sum over the 8 lanes of a row that share bit 0 of the lane index (the 8
+// pairs of an M2L chunk, one component): xor 2, then rotations by 4 and 8.
+__device__ __forceinline__ double sum8_64(double v)
+{
+    v += dpp64<DPP_XOR2>(v);
+    v += dpp64<DPP_ROR4>(v);
+    v += dpp64<DPP_ROR8>(v);
+    return v;
+}
+__device__ __forceinline__ float sum8_32(float v)
+{
+    v += dpp32<DPP_XOR2>(v);
+    v += dpp32<DPP_ROR4>(v);
+    v += dpp32<DPP_ROR8>(v);
+    return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -310,6 +361,15 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
+    // 1/l for the a_0 term of the rows this lane holds (LOG only)
+    double irow[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = 16 * mt + 4 * j + kq;
+            irow[mt][j] = (LOG && row >= 1) ? 1.0 / row : 0.0;
+        }
 
     const int32_t *wl = a.sw ? a.sw : a.widx;
     // the next chunk's list entry is fetched one iteration ahead
@@ -332,7 +392,7 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
         const int ksn = (qc + 3) >> 2, mtn = (qc >> 4) + 1;
         const int64_t gS = bo + sb;
         const double2 r = make_double2(a.centre[2 * gS] - cT.x, a.centre[2 * gS + 1] - cT.y);
-        const double2 rinv = valid ? cinv(r) : make_double2(0.0, 0.0);
+        const double2 rinv = valid ? cinv_fast(r) : make_double2(0.0, 0.0);
         const double2 *As = a.A + gS * P1;
         // pre-scale: lane holds beta_{k'} for k' = 4 ks + kq
         const double2 r2 = cmul(rinv, rinv);
@@ -374,11 +434,11 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
             for (int j = 0; j < 4; ++j) {
                 const int row = 16 * mt + 4 * j + kq;
                 const double mine = C[mt][j];
-                const double oth = __shfl_xor(mine, 1, WAVE);
+                const double oth = dpp64<DPP_XOR1>(mine);
                 double2 Bl = comp ? make_double2(oth, mine) : make_double2(mine, oth);
-                if (row >= 1) {
-                    Bl.x -= a0.x / row;
-                    Bl.y -= a0.y / row;
+                if (LOG) {
+                    Bl.x -= a0.x * irow[mt][j];
+                    Bl.y -= a0.y * irow[mt][j];
                 }
                 const double2 res = cmul(Bl, pr);
                 if (valid && row <= q) acc[mt][j] += comp ? res.y : res.x;
@@ -398,13 +458,7 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double v = acc[mt][j];
-            v += __shfl_xor(v, 2, WAVE);
-            v += __shfl_xor(v, 4, WAVE);
-            v += __shfl_xor(v, 8, WAVE);
-            acc[mt][j] = v;
-        }
+        for (int j = 0; j < 4; ++j) acc[mt][j] = sum8_64(acc[mt][j]);
 }
 
 // One launch: blocks [0, H) take the boxes with more than M2L_HEAVY weak pairs
@@ -506,6 +560,14 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0f;
     acc0 = 0.0;
+    float irow[MT][4]; // 1/l for the a_0 term (LOG only); rows 16 mt + 4 kq + j
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = 16 * mt + 4 * kq + j;
+            irow[mt][j] = (LOG && row >= 1) ? 1.0f / (float)row : 0.0f;
+        }
     const int32_t *wl = a.sw ? a.sw : a.widx;
     // the next chunk's list entry is fetched one iteration ahead
     int32_t sb_next = (e0 + 8 * w + ps < e1) ? wl[e0 + 8 * w + ps] : 0;
@@ -527,7 +589,7 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
         const double sS = scale_radius(a.radius[gS], rmin);
         double2 u64 = make_double2(0.0, 0.0), v64 = make_double2(0.0, 0.0);
         if (valid) {
-            const double2 ri = cinv(r);
+            const double2 ri = cinv_fast(r);
             u64 = make_double2(sS * ri.x, sS * ri.y);
             v64 = make_double2(sT * ri.x, sT * ri.y);
         }
@@ -573,11 +635,11 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
             for (int j = 0; j < 4; ++j) {
                 const int row = 16 * mt + 4 * kq + j;
                 const float mine = C[mt][j];
-                const float oth = __shfl_xor(mine, 1, WAVE);
+                const float oth = dpp32<DPP_XOR1>(mine);
                 float2 Bl = comp ? make_float2(oth, mine) : make_float2(mine, oth);
-                if (row >= 1) {
-                    Bl.x -= a0.x / row;
-                    Bl.y -= a0.y / row;
+                if (LOG) {
+                    Bl.x -= a0.x * irow[mt][j];
+                    Bl.y -= a0.y * irow[mt][j];
                 }
                 const float2 res = cmulf(Bl, pr);
                 if (valid && row <= q) acc[mt][j] += comp ? res.y : res.x;
@@ -594,16 +656,8 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float vv = acc[mt][j];
-            vv += __shfl_xor(vv, 2, WAVE);
-            vv += __shfl_xor(vv, 4, WAVE);
-            vv += __shfl_xor(vv, 8, WAVE);
-            acc[mt][j] = vv;
-        }
-    acc0 += __shfl_xor(acc0, 2, WAVE);
-    acc0 += __shfl_xor(acc0, 4, WAVE);
-    acc0 += __shfl_xor(acc0, 8, WAVE);
+        for (int j = 0; j < 4; ++j) acc[mt][j] = sum8_32(acc[mt][j]);
+    acc0 = sum8_64(acc0);
 }
 
 // b_l = bhat_l / sigma_T^l in FP64, one factor at a time so that no

@@ -491,6 +491,191 @@ __global__ void __launch_bounds__(SCAN_T) k_part_scatter(part_batch pb)
     }
 }
 
+// ------------------------------------------------ subtree in LDS --
+// Evaluation at the sources: once every segment holds at most SUB_S sources,
+// one workgroup takes a segment through all its remaining splits in LDS and
+// writes the box geometry, the per-level starts and the leaf order itself.
+// Local point ids are positions in the segment's (x, index)-ordered list; the
+// (y, index) order of the same points is rebuilt here by a bitonic sort, which
+// gives the same order as the global y list inside the segment.  The split
+// rules are those of the global steps (k_seg, rec_lo) evaluated in the same
+// arithmetic, so the tree is the same.
+#define SUB_S 2048
+#define SUB_T 512
+#define SUB_I (SUB_S / SUB_T)
+
+struct subtree_args {
+    const pt_rec *lx;           // x list after step k0
+    const int32_t *sst;         // starts of the step-k0 segments (nseg0 + 1)
+    int k0, L;
+    int32_t nseg0;
+    int64_t ns;
+    double *centre, *radius;    // all levels
+    int32_t *sstart;            // per-level starts, all levels
+    int32_t *perm;
+};
+
+__global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
+{
+    __shared__ double px[SUB_S], py[SUB_S];
+    __shared__ int32_t pid[SUB_S];
+    __shared__ uint16_t lst[2][2][SUB_S]; // [buffer][x or y list][position] -> local id
+    __shared__ uint16_t st[2][SUB_S + 1]; // [buffer] sub-segment starts
+    __shared__ uint16_t piv[SUB_S];       // pivot local id per sub-segment
+    __shared__ uint8_t axs[SUB_S];
+    __shared__ uint16_t exs[2][SUB_S];    // exclusive scans of the lo flags
+    __shared__ int32_t sh[SUB_T / WAVE];
+    const int tid = threadIdx.x;
+    const int32_t g0 = blockIdx.x;
+    const int32_t base = a.sst[g0];
+    const int32_t n = min(max(a.sst[g0 + 1] - base, 0), SUB_S);
+    for (int i = tid; i < n; i += SUB_T) {
+        const pt_rec r = a.lx[base + i];
+        px[i] = r.x;
+        py[i] = r.y;
+        pid[i] = r.idx;
+    }
+    for (int i = tid; i < SUB_S; i += SUB_T) {
+        lst[0][0][i] = (uint16_t)i;
+        lst[0][1][i] = (uint16_t)i;
+    }
+    if (tid == 0) {
+        st[0][0] = 0;
+        st[0][1] = (uint16_t)n;
+    }
+    __syncthreads();
+    // (y, index) order: bitonic sort of the local ids; ids >= n sort last
+    for (int k = 2; k <= SUB_S; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < SUB_S; i += SUB_T) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint16_t u = lst[0][1][i], v = lst[0][1][l];
+                    bool gt; // key(u) > key(v)
+                    if (u >= n || v >= n) gt = u >= n && (v < n || u > v);
+                    else gt = py[u] > py[v] || (py[u] == py[v] && pid[u] > pid[v]);
+                    if (((i & k) == 0) == gt) {
+                        lst[0][1][i] = v;
+                        lst[0][1][l] = u;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int J = 2 * a.L - a.k0;
+    int cur = 0;
+    for (int j = 0; j <= J; ++j) {
+        const int32_t nsub = 1 << j;
+        const int kg = a.k0 + j;
+        const bool even = (kg & 1) == 0, split = j < J;
+        const int lev = kg >> 1;
+        // (a) per sub-segment: rectangle, geometry on even steps, axis and pivot
+        for (int32_t t = tid; t < nsub; t += SUB_T) {
+            const int32_t s0 = st[cur][t], s1 = st[cur][t + 1], m = s1 - s0;
+            double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+            if (m > 0) {
+                x0 = px[lst[cur][0][s0]];
+                x1 = px[lst[cur][0][s1 - 1]];
+                y0 = py[lst[cur][1][s0]];
+                y1 = py[lst[cur][1][s1 - 1]];
+            }
+            const double w = x1 - x0, h = y1 - y0;
+            if (even) {
+                const int64_t b = ((int64_t)g0 << j) + t;
+                const int64_t gb = d_box_off(lev) + b;
+                a.centre[2 * gb] = 0.5 * (x0 + x1);
+                a.centre[2 * gb + 1] = 0.5 * (y0 + y1);
+                a.radius[gb] = 0.5 * sqrt(w * w + h * h);
+                a.sstart[d_start_off(lev) + b] = base + s0;
+                if (g0 == a.nseg0 - 1 && t == nsub - 1)
+                    a.sstart[d_start_off(lev) + (((int64_t)1) << (2 * lev))] = (int32_t)a.ns;
+            }
+            if (split) {
+                const int ax = (w >= h) ? 0 : 1;
+                axs[t] = (uint8_t)ax;
+                piv[t] = m > 0 ? lst[cur][ax][s0 + m / 2] : 0;
+            }
+        }
+        __syncthreads();
+        if (!split) break;
+        const int nxt = cur ^ 1;
+        // (b) lo flags of both lists, block-wide exclusive scans
+        bool lo[2][SUB_I];
+        int32_t tseg[2][SUB_I];
+        for (int q = 0; q < 2; ++q) {
+            int32_t cnt = 0;
+#pragma unroll
+            for (int u = 0; u < SUB_I; ++u) {
+                const int p = tid * SUB_I + u;
+                bool f = false;
+                int32_t t = 0;
+                if (p < n) {
+                    // sub-segment of position p: the last t with st[t] <= p
+                    int32_t lo_t = 0, hi_t = nsub - 1;
+                    while (lo_t < hi_t) {
+                        const int32_t mid = (lo_t + hi_t + 1) >> 1;
+                        if (st[cur][mid] <= p) lo_t = mid; else hi_t = mid - 1;
+                    }
+                    t = lo_t;
+                    const uint16_t id = lst[cur][q][p], pv = piv[t];
+                    const double c = axs[t] ? py[id] : px[id];
+                    const double pc = axs[t] ? py[pv] : px[pv];
+                    f = c < pc || (c == pc && pid[id] < pid[pv]);
+                }
+                lo[q][u] = f;
+                tseg[q][u] = t;
+                cnt += f;
+            }
+            int32_t tot;
+            int32_t e = block_excl_scan(cnt, sh, &tot);
+#pragma unroll
+            for (int u = 0; u < SUB_I; ++u) {
+                const int p = tid * SUB_I + u;
+                if (p < n) exs[q][p] = (uint16_t)e;
+                e += lo[q][u];
+            }
+        }
+        __syncthreads();
+        // (c) stable partition of both lists into the other buffer
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int u = 0; u < SUB_I; ++u) {
+                const int p = tid * SUB_I + u;
+                if (p < n) {
+                    const int32_t t = tseg[q][u];
+                    const int32_t s0 = st[cur][t], m = st[cur][t + 1] - s0;
+                    const int32_t r = exs[q][p] - exs[q][s0]; // lo positions before p in t
+                    const int32_t dst = lo[q][u] ? s0 + r : s0 + m / 2 + (p - s0 - r);
+                    lst[nxt][q][min(max(dst, 0), SUB_S - 1)] = lst[cur][q][p];
+                }
+            }
+        }
+        for (int32_t t = tid; t < nsub; t += SUB_T) {
+            const int32_t s0 = st[cur][t], m = st[cur][t + 1] - s0;
+            st[nxt][2 * t] = (uint16_t)s0;
+            st[nxt][2 * t + 1] = (uint16_t)(s0 + m / 2);
+        }
+        if (tid == 0) st[nxt][2 * nsub] = (uint16_t)n;
+        __syncthreads();
+        cur = nxt;
+    }
+    // (d) leaf order: inside every leaf the sources by ascending original index
+    const int32_t nleaf = 1 << J;
+    for (int p = tid; p < n; p += SUB_T) {
+        int32_t lo_t = 0, hi_t = nleaf - 1;
+        while (lo_t < hi_t) {
+            const int32_t mid = (lo_t + hi_t + 1) >> 1;
+            if (st[cur][mid] <= p) lo_t = mid; else hi_t = mid - 1;
+        }
+        const int32_t s0 = st[cur][lo_t], s1 = st[cur][lo_t + 1];
+        const int32_t me = pid[lst[cur][0][p]];
+        int32_t r = 0;
+        for (int32_t k = s0; k < s1; ++k) r += pid[lst[cur][0][k]] < me;
+        a.perm[base + s0 + min(r, s1 - s0 - 1)] = me;
+    }
+}
+
 // Leaf of every original index (as the sort key) and the identity values.
 __global__ void k_leaf_keys(const pt_rec *__restrict__ lx, int64_t n, uint64_t *__restrict__ keys,
                             int32_t *__restrict__ vals)
@@ -671,7 +856,7 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     const fmm_layout &lay = *a.lay;
     const int L = a.L;
     const int64_t ns = a.ns, nt = a.nt;
-    uint64_t *k0 = WS(uint64_t, lay.keys[0]), *k1 = WS(uint64_t, lay.keys[1]);
+    uint64_t *k0s = WS(uint64_t, lay.keys[0]), *k1 = WS(uint64_t, lay.keys[1]);
     int32_t *v0 = WS(int32_t, lay.vals[0]), *v1 = WS(int32_t, lay.vals[1]);
     int32_t *hist = WS(int32_t, lay.hist);
     int32_t *bsum = WS(int32_t, lay.bsum);
@@ -692,20 +877,45 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     double *centre = WS(double, lay.centre), *radius = WS(double, lay.radius);
 
     // presort into (coordinate, index) order, then records
-    CK(presort(a.src, ns, 0, k0, k1, v0, v1, hist, bsum, perm, st));
+    CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, perm, st));
     k_rec_init<<<nblk256(ns), 256, 0, st>>>(a.src, perm, ns, sl[0]);
-    CK(presort(a.src, ns, 1, k0, k1, v0, v1, hist, bsum, perm, st));
+    CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, perm, st));
     k_rec_init<<<nblk256(ns), 256, 0, st>>>(a.src, perm, ns, sl[1]);
     if (nt) {
-        CK(presort(a.tgt, nt, 0, k0, k1, v0, v1, hist, bsum, tperm, st));
+        CK(presort(a.tgt, nt, 0, k0s, k1, v0, v1, hist, bsum, tperm, st));
         k_rec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[0]);
-        CK(presort(a.tgt, nt, 1, k0, k1, v0, v1, hist, bsum, tperm, st));
+        CK(presort(a.tgt, nt, 1, k0s, k1, v0, v1, hist, bsum, tperm, st));
         k_rec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[1]);
     }
     k_root<<<1, 1, 0, st>>>(sstep, (int32_t)ns, tstep, (int32_t)nt);
+    // At the sources, the steps from k0 on run in LDS (k_subtree): k0 is the
+    // first step whose segments (at most ceil(ns / 2^k) sources) fit.
+    int k0 = -1;
+    if (nt == 0)
+        for (int k = 0; k <= 2 * L; ++k)
+            if (((ns + (((int64_t)1) << k) - 1) >> k) <= SUB_S && (((int64_t)1) << (2 * L - k)) <= SUB_S) {
+                k0 = k;
+                break;
+            }
     int64_t soff_k = 0; // offset of step k's starts
     for (int k = 0; k <= 2 * L; ++k) {
         const int32_t nseg = (int32_t)(((int64_t)1) << k);
+        if (k == k0) {
+            subtree_args ta;
+            ta.lx = sl[0];
+            ta.sst = sstep + soff_k;
+            ta.k0 = k0;
+            ta.L = L;
+            ta.nseg0 = nseg;
+            ta.ns = ns;
+            ta.centre = centre;
+            ta.radius = radius;
+            ta.sstart = sstart;
+            ta.perm = perm;
+            k_subtree<<<(unsigned)nseg, SUB_T, 0, st>>>(ta);
+            CK(hipGetLastError());
+            break;
+        }
         const bool split = k < 2 * L;
         const bool even = (k % 2) == 0;
         const int l = k / 2;
@@ -764,12 +974,14 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     // leaf order with ascending original index inside every leaf: a stable
     // sort of the identity by leaf number
     const int passes = (2 * L + 7) / 8;
-    k_leaf_keys<<<nblk256(ns), 256, 0, st>>>(sl[0], ns, k0, v0);
-    if (passes > 0) CK(radix_sort(ns, passes, k0, k1, v0, v1, hist, bsum, perm, st));
-    else CK(hipMemcpyAsync(perm, v0, (size_t)ns * 4, hipMemcpyDeviceToDevice, st));
+    if (k0 < 0) {
+        k_leaf_keys<<<nblk256(ns), 256, 0, st>>>(sl[0], ns, k0s, v0);
+        if (passes > 0) CK(radix_sort(ns, passes, k0s, k1, v0, v1, hist, bsum, perm, st));
+        else CK(hipMemcpyAsync(perm, v0, (size_t)ns * 4, hipMemcpyDeviceToDevice, st));
+    }
     if (nt) {
-        k_leaf_keys<<<nblk256(nt), 256, 0, st>>>(tl[0], nt, k0, v0);
-        if (passes > 0) CK(radix_sort(nt, passes, k0, k1, v0, v1, hist, bsum, tperm, st));
+        k_leaf_keys<<<nblk256(nt), 256, 0, st>>>(tl[0], nt, k0s, v0);
+        if (passes > 0) CK(radix_sort(nt, passes, k0s, k1, v0, v1, hist, bsum, tperm, st));
         else CK(hipMemcpyAsync(tperm, v0, (size_t)nt * 4, hipMemcpyDeviceToDevice, st));
     }
     {

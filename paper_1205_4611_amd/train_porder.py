@@ -13,7 +13,7 @@ Recipe (everything seeded and synthetic):
      and deviation, trained with the pinball loss at quantile tau on the GPU
      (fmm2d_mlp_grad, fmm2d_mlp_adam), minibatches, cosine learning rate.
   3. delta: on the held-out seed, the smallest offset on a grid whose
-     evaluation with learned orders (storage order p, FP32 far field) keeps the
+     evaluation with learned orders (storage order p, FP64) keeps the
      pointwise relative error of Phi' at 10,000 sampled sources (device direct
      sum) below margin * tol.
 The result is a JSON file with the 353 model floats, delta and the recipe.
@@ -53,7 +53,7 @@ def main():
     ap.add_argument("--batch", type=int, default=1 << 16)
     ap.add_argument("--lr", type=float, default=1e-2)
     ap.add_argument("--margin", type=float, default=0.5)
-    ap.add_argument("--precision", default="mixed_far")
+    ap.add_argument("--precision", default="fp64")
     args = ap.parse_args()
 
     import torch
@@ -128,7 +128,7 @@ def main():
     print("validation fixed p=%d (%s): err_pt %.3e" % (args.p, args.precision, err_fixed), flush=True)
     chosen = None
     trials = []
-    for delta in (-1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0):
+    for delta in (-2.0, -1.5, -1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0):
         f.set_porder_model(model, delta)
         _, d = f.eval(src, mm, p=args.p, levels=L, kernel="harmonic", swap=True, precision=args.precision,
                       porder="learned")

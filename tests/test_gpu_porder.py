@@ -220,8 +220,8 @@ def _range_bounds(w, Fo):
     for i in range(8):
         u = np.unique(Fo[:, i])
         for side, (a, b) in ((16, (0.01, 0.05)), (24, (0.95, 0.99))):
-            if u.size < 2:
-                w[o + side + i] = u[0] - 1 if side == 16 else u[0] + 1
+            if u.size < 50:   # a discrete feature: keep all of it in range
+                w[o + side + i] = u[0] - 1 if side == 16 else u[-1] + 1
                 continue
             j0 = int(a * (u.size - 1))
             j1 = min(max(int(b * (u.size - 1)), j0 + 1), u.size - 1)
