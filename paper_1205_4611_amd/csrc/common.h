@@ -14,6 +14,7 @@
 // status bits written by kernels into the handle's device status word
 #define FMM_ST_LIST_OVERFLOW 1
 #define FMM_ST_ORDERS_SHORT 2   // caller's pair orders shorter than the weak list
+#define FMM_ST_TREE_INCONSISTENT 4 // internal check of the tree build failed
 
 // learned truncation order
 #define FMM_NF FMM2D_PORDER_NFEAT
@@ -71,8 +72,11 @@ struct fmm_layout {
     size_t A32;                  // FP32 radius-scaled multipoles (mixed)
     size_t n1, tail;             // per-box coefficient norms (order features)
     size_t vmin, budget;         // per-box label budget
+    size_t hs, hoff, hbox, hpart; // M2L heavy-box segments (counts, offsets, box, partials)
+    int64_t hmax;                // capacity in segments
     size_t qw;                   // uint8 order per weak pair, weak-list order
     size_t sw, sp;               // weak pairs sorted by order within a box: source, order
+    size_t pbox;                 // target box of every weak pair (order phase)
     size_t total;
 };
 
@@ -111,7 +115,10 @@ struct fmm_eval_args {
 };
 hipError_t fmm_p2m(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_m2m(const fmm_eval_args &a, hipStream_t st);
+hipError_t fmm_m2l_plan(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st);
+#define FMM_M2L_HEAVY 256  // weak pairs above which a box is cut into segments
+#define FMM_M2L_SEG 512    // pairs per segment
 hipError_t fmm_l2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_p2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_p2p_l2p(const fmm_eval_args &a, double *phi, double *dphi, hipStream_t st);
@@ -119,6 +126,9 @@ hipError_t fmm_p2p_l2p(const fmm_eval_args &a, double *phi, double *dphi, hipStr
 // learned / given per-pair orders (porder.hip)
 struct fmm_porder_args {
     const double *centre, *radius, *n1, *tail;
+    double *den;                  // per-box share denominators (scratch)
+    double *dpart;                // heavy-segment partial denominators (scratch)
+    int32_t *pbox;                // target box of every weak pair (scratch)
     const int32_t *woff, *widx;
     const float *model;           // device model or NULL
     float delta;
@@ -131,6 +141,8 @@ struct fmm_porder_args {
     int32_t *sw;
     uint8_t *sp;
     int32_t *status;
+    const int32_t *hoff, *hbox;   // M2L heavy-box segments (the sort's units)
+    int64_t hmax;
 };
 hipError_t fmm_box_norms(const double2 *A, const double *radius, int p, int64_t nb, double *n1, double *tail,
                          hipStream_t st);

@@ -18,6 +18,8 @@
 // it describes.)  S is the same for every pair, so it stays in registers as
 // the MFMA A operand while the pre-scaled multipoles of 8 pairs (16 real
 // columns: re/im) stream through the B operand.
+#include <string.h>
+
 #include "common.h"
 
 #define WAVE 64
@@ -80,6 +82,14 @@ __device__ __forceinline__ double sum8_64(double v)
     v += dpp64<DPP_XOR2>(v);
     v += dpp64<DPP_ROR4>(v);
     v += dpp64<DPP_ROR8>(v);
+    return v;
+}
+// Largest value over the same 8 lanes (the pairs of a chunk).
+__device__ __forceinline__ int max8_i(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_XOR2, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_ROR4, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_ROR8, 0xF, 0xF, false));
     return v;
 }
 __device__ __forceinline__ float sum8_32(float v)
@@ -305,6 +315,11 @@ struct m2l_args {
     int64_t nb;
     int L, p, kernel;
     int32_t cap;
+    // boxes with more than M2L_HEAVY weak pairs are cut into segments of
+    // M2L_SEG pairs: hoff[g] = first segment of box g (exclusive scan, total
+    // at hoff[nb]), hbox[s] = box of segment s, hpart[s][p+1] its partial sum
+    const int32_t *hoff, *hbox;
+    double2 *hpart;
 };
 
 __device__ __forceinline__ int level_of(int64_t g, int L)
@@ -319,7 +334,8 @@ __device__ __forceinline__ double2 clog_principal(double2 z)
     return make_double2(0.5 * log(z.x * z.x + z.y * z.y), atan2(z.y, z.x));
 }
 
-#define M2L_HEAVY 256 // boxes with more weak pairs get an 8-wave workgroup
+#define M2L_HEAVY FMM_M2L_HEAVY // boxes with more weak pairs are cut into segments
+#define M2L_SEG FMM_M2L_SEG     // pairs per segment (one 8-wave workgroup each)
 #define M2L_WAVES 8
 
 __device__ __forceinline__ int32_t m2l_range(const m2l_args &a, int64_t g, int &l, int32_t &e0, int32_t &e1)
@@ -332,23 +348,81 @@ __device__ __forceinline__ int32_t m2l_range(const m2l_args &a, int64_t g, int &
     return e1 - e0;
 }
 
+// Radius used to scale the FP32 coefficients: the box radius, floored.
+__device__ __forceinline__ double scale_radius(double rho, double rmin)
+{
+    return rho > rmin ? rho : rmin;
+}
+// Scaling radius floor: 2^-40 of the root radius (boxes of coincident points
+// have radius 0; any positive scale is exact in exact arithmetic).
+__device__ __forceinline__ double scale_floor(const double *radius)
+{
+    return fmax(radius[0] * 0x1p-40, 1e-300);
+}
+
+// Operands of one chunk of 8 pairs as this lane needs them, fetched one chunk
+// ahead of its use (the list entry two chunks ahead) so that the loads of the
+// next chunk overlap the contraction of the current one.
+template <int KS, typename C2>
+struct m2l_chunk {
+    double2 cS;       // source centre
+    C2 ak[KS];        // a_k (or ahat_k), k = 4 ks + kq + 1
+    double2 a0;       // a_0 (log kernel)
+    double sS;        // source scaling radius (FP32 path)
+    int q, qc;        // this pair's order, the chunk's largest order
+    bool valid;
+};
+
+template <int KS, bool LOG, bool F32, typename C2>
+__device__ __forceinline__ void m2l_fetch(const m2l_args &a, int64_t bo, int32_t nbl, int32_t e, int32_t e1,
+                                          int32_t sbraw, int ps, int kq, double rmin, m2l_chunk<KS, C2> &c)
+{
+    const int p = a.p, P1 = p + 1;
+    const int32_t pe = e + ps;
+    c.valid = pe < e1;
+    const int32_t sb = min(max(c.valid ? sbraw : 0, 0), nbl - 1);
+    const int64_t gS = bo + sb;
+    c.cS = make_double2(a.centre[2 * gS], a.centre[2 * gS + 1]);
+    c.q = p;
+    c.qc = p;
+    if (a.sp) {
+        c.q = c.valid ? (int)a.sp[pe] : 0;
+        // the chunk's largest order bounds its k-steps and row tiles
+        c.qc = __builtin_amdgcn_readfirstlane(max8_i(c.q));
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int kk = 4 * ks + kq + 1;
+        if (F32) {
+            const float2 *As = a.A32 + gS * P1;
+            const float2 v = (c.valid && kk <= p) ? As[kk] : make_float2(0.0f, 0.0f);
+            c.ak[ks] = *reinterpret_cast<const C2 *>(&v);
+        } else {
+            const double2 *As = a.A + gS * P1;
+            const double2 v = (c.valid && kk <= p) ? As[kk] : make_double2(0.0, 0.0);
+            c.ak[ks] = *reinterpret_cast<const C2 *>(&v);
+        }
+    }
+    c.a0 = (LOG && c.valid) ? a.A[gS * P1] : make_double2(0.0, 0.0);
+    c.sS = F32 ? scale_radius(a.radius[gS], rmin) : 0.0;
+}
+
 // FP64 contraction for the chunks c = w, w + nw, ... of 8 weak pairs of box g.
 // Lane layout of v_mfma_f64_16x16x4f64: A operand lane i holds A[i%16][i/16],
 // B operand lane i holds B[i/16][i%16], accumulator element j of lane i holds
 // row 4j + i/16 of column i%16 (the FP64 instruction interleaves its rows).
 // On return acc[mt][j] holds, summed over this lane's pairs, the re (even
 // column) or im (odd column) part of b_l, l = 16 mt + 4 j + kq.
-template <int MT, int KS>
+template <int MT, int KS, bool LOG>
 __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, int32_t e0, int32_t e1, int w,
                                           int nw, double (&acc)[MT][4])
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t bo = d_box_off(l);
-    const int p = a.p, P1 = p + 1;
+    const int p = a.p;
     const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
     const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
     const double2 cT = make_double2(a.centre[2 * g], a.centre[2 * g + 1]);
-    const bool LOG = a.kernel == FMM2D_KERNEL_LOG;
     double Sop[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -361,7 +435,7 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
-    // 1/l for the a_0 term of the rows this lane holds (LOG only)
+    // 1/l for the a_0 term of the rows this lane holds (log kernel)
     double irow[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -370,88 +444,97 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
             const int row = 16 * mt + 4 * j + kq;
             irow[mt][j] = (LOG && row >= 1) ? 1.0 / row : 0.0;
         }
-
     const int32_t *wl = a.sw ? a.sw : a.widx;
-    // the next chunk's list entry is fetched one iteration ahead
-    int32_t sb_next = (e0 + 8 * w + ps < e1) ? wl[e0 + 8 * w + ps] : 0;
-    for (int32_t e = e0 + 8 * w; e < e1; e += 8 * nw) {
-        const int32_t pe = e + ps;
-        const bool valid = pe < e1;
-        int32_t sb = valid ? sb_next : 0;
-        const int32_t pn = pe + 8 * nw;
-        sb_next = (pn < e1) ? wl[pn] : 0;
-        sb = min(max(sb, 0), nbl - 1);
-        // order of this lane's pair (q) and the largest order of the chunk
-        // (qc, its last pair: orders ascend within a box), which bounds the
-        // k-steps and row tiles the chunk needs
-        int q = p, qc = p;
-        if (a.sp) {
-            q = valid ? (int)a.sp[pe] : 0;
-            qc = __builtin_amdgcn_readfirstlane((int)a.sp[min(e + 7, e1 - 1)]);
-        }
-        const int ksn = (qc + 3) >> 2, mtn = (qc >> 4) + 1;
-        const int64_t gS = bo + sb;
-        const double2 r = make_double2(a.centre[2 * gS] - cT.x, a.centre[2 * gS + 1] - cT.y);
-        const double2 rinv = valid ? cinv_fast(r) : make_double2(0.0, 0.0);
-        const double2 *As = a.A + gS * P1;
-        // pre-scale: lane holds beta_{k'} for k' = 4 ks + kq
-        const double2 r2 = cmul(rinv, rinv);
-        const double2 r4 = cmul(r2, r2);
-        double2 pw = rinv;
-        for (int t = 0; t < kq; ++t) pw = cmul(pw, rinv);
-        double bop[KS];
+    const int32_t step = 8 * nw;
+    int32_t e = e0 + 8 * w;
+    if (e < e1) {
+        int32_t sb1 = (e + step + ps < e1) ? wl[e + step + ps] : 0;
+        m2l_chunk<KS, double2> cur;
+        m2l_fetch<KS, LOG, false>(a, bo, nbl, e, e1, (e + ps < e1) ? wl[e + ps] : 0, ps, kq, 0.0, cur);
+        for (; e < e1; e += step) {
+            // prefetch: the list entry two chunks ahead, the operands of the next
+            const int32_t en = e + step;
+            const int32_t sb2 = (en + step + ps < e1) ? wl[en + step + ps] : 0;
+            m2l_chunk<KS, double2> nxt;
+            m2l_fetch<KS, LOG, false>(a, bo, nbl, en, e1, sb1, ps, kq, 0.0, nxt);
+            sb1 = sb2;
+
+            const bool valid = cur.valid;
+            const int qlim = valid ? cur.q : -1; // rows and k-terms above this order are dropped
+            const int ksn = (cur.qc + 3) >> 2, mtn = (cur.qc >> 4) + 1;
+            const double2 r = make_double2(cur.cS.x - cT.x, cur.cS.y - cT.y);
+            const double2 r1 = valid ? cinv_fast(r) : make_double2(0.0, 0.0);
+            const double2 r2 = cmul(r1, r1), r3 = cmul(r2, r1), r4 = cmul(r2, r2);
+            // This lane needs one component (comp) of complex products only.
+            // Pre-scale: bop[ks] = comp part of (-1)^{k'+1} a_{k'+1} r^{-(k'+1)},
+            // k' = 4 ks + kq, written as a.x w1 + a.y w2; multiplying the power
+            // by r^-4 maps (w1, w2) -> (w1 c + w2 d, w2 c - w1 d), r^-4 = c + i d.
+            const double2 p0 = kq == 0 ? r1 : (kq == 1 ? r2 : (kq == 2 ? r3 : r4)); // r^{-(kq+1)}
+            const double sg = (kq & 1) ? 1.0 : -1.0;                                // (-1)^{kq+1}
+            double w1 = comp ? sg * p0.y : sg * p0.x;
+            double w2 = comp ? sg * p0.x : -sg * p0.y;
+            double bop[KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int kk = 4 * ks + kq + 1;
-            bop[ks] = 0.0;
-            if (ks < ksn) {
-                const double2 ak = (valid && kk <= q) ? As[kk] : make_double2(0.0, 0.0);
-                double2 v = cmul(ak, pw);
-                if (kk & 1) { v.x = -v.x; v.y = -v.y; }
-                bop[ks] = comp ? v.y : v.x;
-                pw = cmul(pw, r4);
-            }
-        }
-        dbl4 C[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) C[mt] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                if (ks < ksn && mt < mtn)
-                    C[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
-        // post-scale: row l = 16 mt + 4 j + kq gets r^{-l} (B_l - a_0/l)
-        const double2 a0 = (valid && LOG) ? As[0] : make_double2(0.0, 0.0);
-        const double2 r16 = cmul(cmul(r4, r4), cmul(r4, r4));
-        double2 base = make_double2(1.0, 0.0);
-        for (int t = 0; t < kq; ++t) base = cmul(base, rinv);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            if (mt >= mtn) break;
-            double2 pr = base;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = 16 * mt + 4 * j + kq;
-                const double mine = C[mt][j];
-                const double oth = dpp64<DPP_XOR1>(mine);
-                double2 Bl = comp ? make_double2(oth, mine) : make_double2(mine, oth);
-                if (LOG) {
-                    Bl.x -= a0.x * irow[mt][j];
-                    Bl.y -= a0.y * irow[mt][j];
+            for (int ks = 0; ks < KS; ++ks) {
+                bop[ks] = 0.0;
+                if (ks < ksn) {
+                    const double2 ak = cur.ak[ks];
+                    bop[ks] = (4 * ks + kq + 1 <= qlim) ? fma(ak.y, w2, ak.x * w1) : 0.0;
+                    const double t = fma(w2, r4.y, w1 * r4.x);
+                    w2 = fma(-w1, r4.y, w2 * r4.x);
+                    w1 = t;
                 }
-                const double2 res = cmul(Bl, pr);
-                if (valid && row <= q) acc[mt][j] += comp ? res.y : res.x;
-                pr = cmul(pr, r4);
             }
-            base = cmul(base, r16);
-        }
-        if (LOG && valid && kq == 0) {
-            // Log(c_T - c_S), the difference formed as written: on the branch
-            // cut the sign of a zero imaginary part decides between +pi and -pi
-            const double2 lg = clog_principal(make_double2(cT.x - a.centre[2 * gS], cT.y - a.centre[2 * gS + 1]));
-            const double2 t = cmul(a0, lg);
-            acc[0][0] += comp ? t.y : t.x;
+            dbl4 C[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) C[mt] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    if (ks < ksn && mt < mtn)
+                        C[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
+            // Post-scale: row l = 16 mt + 4 j + kq gets r^{-l} (B_l - a_0/l);
+            // with (mine, oth) the lane's and the other component of B_l, the
+            // lane's part is mine v1 + oth v2, (v1, v2) = (Re, +-Im) of r^{-l}.
+            const double2 b0 = kq == 0 ? make_double2(1.0, 0.0) : (kq == 1 ? r1 : (kq == 2 ? r2 : r3)); // r^{-kq}
+            const double sc = comp ? 1.0 : -1.0;
+            const double d4 = sc * r4.y;
+            const double2 r8 = cmul(r4, r4), r16 = cmul(r8, r8);
+            const double d16 = sc * r16.y;
+            double u1 = b0.x, u2 = sc * b0.y;
+            const double a0m = comp ? cur.a0.y : cur.a0.x, a0o = comp ? cur.a0.x : cur.a0.y;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                if (mt >= mtn) break;
+                double v1 = u1, v2 = u2;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = 16 * mt + 4 * j + kq;
+                    double mine = C[mt][j];
+                    double oth = dpp64<DPP_XOR1>(mine);
+                    if (LOG) {
+                        mine = fma(-a0m, irow[mt][j], mine);
+                        oth = fma(-a0o, irow[mt][j], oth);
+                    }
+                    const double res = fma(oth, v2, mine * v1);
+                    acc[mt][j] += (row <= qlim) ? res : 0.0;
+                    const double t = fma(-v2, d4, v1 * r4.x);
+                    v2 = fma(v1, d4, v2 * r4.x);
+                    v1 = t;
+                }
+                const double t = fma(-u2, d16, u1 * r16.x);
+                u2 = fma(u1, d16, u2 * r16.x);
+                u1 = t;
+            }
+            if (LOG && valid && kq == 0) {
+                // Log(c_T - c_S), the difference formed as written: on the branch
+                // cut the sign of a zero imaginary part decides between +pi and -pi
+                const double2 lg = clog_principal(make_double2(cT.x - cur.cS.x, cT.y - cur.cS.y));
+                const double2 t = cmul(cur.a0, lg);
+                acc[0][0] += comp ? t.y : t.x;
+            }
+            cur = nxt;
         }
     }
     // sum over the 8 pairs of a tile (lane bits 1..3)
@@ -464,7 +547,7 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, i
 // One launch: blocks [0, H) take the boxes with more than M2L_HEAVY weak pairs
 // (M2L_WAVES waves per box, fixed-order LDS reduction); the other blocks take
 // the light boxes, one wave per box.
-template <int MT, int KS>
+template <int MT, int KS, bool LOG>
 __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
 {
     __shared__ double part[M2L_WAVES][MT * 16][2];
@@ -479,7 +562,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
         int32_t e0, e1;
         if (m2l_range(a, g, l, e0, e1) > M2L_HEAVY) return;
         double acc[MT][4];
-        m2l64_acc<MT, KS>(a, g, l, e0, e1, 0, 1, acc);
+        m2l64_acc<MT, KS, LOG>(a, g, l, e0, e1, 0, 1, acc);
         double2 *Bt = a.B + g * P1;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -489,12 +572,16 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
                 if (ps == 0 && row <= a.p) reinterpret_cast<double *>(Bt + row)[comp] = acc[mt][j];
             }
     } else {
-        for (int64_t g = blockIdx.x; g < a.nb; g += H) {
+        // segments of the heavy boxes; partial sums go to hpart
+        const int32_t nseg = a.hoff[a.nb];
+        for (int32_t sg = blockIdx.x; sg < nseg; sg += H) {
+            const int64_t g = a.hbox[sg];
             int l;
             int32_t e0, e1;
-            if (m2l_range(a, g, l, e0, e1) <= M2L_HEAVY) continue;
+            m2l_range(a, g, l, e0, e1);
+            const int32_t s0 = min(e0 + (sg - a.hoff[g]) * M2L_SEG, e1), s1 = min(s0 + M2L_SEG, e1);
             double acc[MT][4];
-            m2l64_acc<MT, KS>(a, g, l, e0, e1, w, M2L_WAVES, acc);
+            m2l64_acc<MT, KS, LOG>(a, g, l, s0, s1, w, M2L_WAVES, acc);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -502,7 +589,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
                     if (ps == 0) part[w][16 * mt + 4 * j + kq][comp] = acc[mt][j];
             __syncthreads();
             if (w == 0) {
-                double2 *Bt = a.B + g * P1;
+                double2 *Bt = a.hpart + (int64_t)sg * P1;
                 for (int k = lane; k < 2 * P1; k += WAVE) {
                     double v = 0.0;
                     for (int q = 0; q < M2L_WAVES; ++q) v += part[q][k >> 1][k & 1];
@@ -514,39 +601,27 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
     }
 }
 
-// FP32 (mixed precision): the same contraction on v_mfma_f32_16x16x4f32 with
-// radius-scaled coefficients.  With sigma_S, sigma_T the box radii,
-// ahat_k = a_k / sigma_S^k, u = sigma_S / r and v = sigma_T / r:
+// Accumulator layout of v_mfma_f32_16x16x4f32: element j of lane i holds row
+// 4 (i/16) + j of column i%16.  acc0 collects the FP64 a_0 Log term of row 0.
+// FP32 (mixed precision): the same contraction with radius-scaled
+// coefficients.  With sigma_S, sigma_T the box radii, ahat_k = a_k /
+// sigma_S^k, u = sigma_S / r and v = sigma_T / r:
 //   beta_{k'} = (-1)^{k'+1} ahat_{k'+1} u^{k'+1},
 //   bhat_l    = v^l (B_l - a_0/l),   b_l = bhat_l / sigma_T^l.
 // The theta-criterion keeps |u|, |v| <= theta/(1+theta) < 1, so every scaled
 // quantity stays O(1) in FP32.  Log(c_T - c_S) and the final unscaling are FP64.
-__device__ __forceinline__ double scale_radius(double rho, double rmin)
-{
-    return rho > rmin ? rho : rmin;
-}
-// Scaling radius floor: 2^-40 of the root radius (boxes of coincident points
-// have radius 0; any positive scale is exact in exact arithmetic).
-__device__ __forceinline__ double scale_floor(const double *radius)
-{
-    return fmax(radius[0] * 0x1p-40, 1e-300);
-}
-
-// Accumulator layout of v_mfma_f32_16x16x4f32: element j of lane i holds row
-// 4 (i/16) + j of column i%16.  acc0 collects the FP64 a_0 Log term of row 0.
-template <int MT, int KS>
+template <int MT, int KS, bool LOG>
 __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, int32_t e0, int32_t e1, int w,
                                           int nw, float (&acc)[MT][4], double &acc0)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t bo = d_box_off(l);
-    const int p = a.p, P1 = p + 1;
+    const int p = a.p;
     const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
     const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
     const double2 cT = make_double2(a.centre[2 * g], a.centre[2 * g + 1]);
     const double rmin = scale_floor(a.radius);
     const double sT = scale_radius(a.radius[g], rmin);
-    const bool LOG = a.kernel == FMM2D_KERNEL_LOG;
     float Sop[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -560,7 +635,7 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0f;
     acc0 = 0.0;
-    float irow[MT][4]; // 1/l for the a_0 term (LOG only); rows 16 mt + 4 kq + j
+    float irow[MT][4]; // 1/l for the a_0 term (log kernel); rows 16 mt + 4 kq + j
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -569,88 +644,94 @@ __device__ __forceinline__ void m2l32_acc(const m2l_args &a, int64_t g, int l, i
             irow[mt][j] = (LOG && row >= 1) ? 1.0f / (float)row : 0.0f;
         }
     const int32_t *wl = a.sw ? a.sw : a.widx;
-    // the next chunk's list entry is fetched one iteration ahead
-    int32_t sb_next = (e0 + 8 * w + ps < e1) ? wl[e0 + 8 * w + ps] : 0;
-    for (int32_t e = e0 + 8 * w; e < e1; e += 8 * nw) {
-        const int32_t pe = e + ps;
-        const bool valid = pe < e1;
-        int32_t sb = valid ? sb_next : 0;
-        const int32_t pn = pe + 8 * nw;
-        sb_next = (pn < e1) ? wl[pn] : 0;
-        sb = min(max(sb, 0), nbl - 1);
-        int q = p, qc = p; // as in the FP64 kernel
-        if (a.sp) {
-            q = valid ? (int)a.sp[pe] : 0;
-            qc = __builtin_amdgcn_readfirstlane((int)a.sp[min(e + 7, e1 - 1)]);
-        }
-        const int ksn = (qc + 3) >> 2, mtn = (qc >> 4) + 1;
-        const int64_t gS = bo + sb;
-        const double2 r = make_double2(a.centre[2 * gS] - cT.x, a.centre[2 * gS + 1] - cT.y);
-        const double sS = scale_radius(a.radius[gS], rmin);
-        double2 u64 = make_double2(0.0, 0.0), v64 = make_double2(0.0, 0.0);
-        if (valid) {
-            const double2 ri = cinv_fast(r);
-            u64 = make_double2(sS * ri.x, sS * ri.y);
-            v64 = make_double2(sT * ri.x, sT * ri.y);
-        }
-        const float2 u = make_float2((float)u64.x, (float)u64.y);
-        const float2 v = make_float2((float)v64.x, (float)v64.y);
-        const float2 *As = a.A32 + gS * P1;
-        const float2 u2 = cmulf(u, u), u4 = cmulf(u2, u2);
-        float2 pw = u;
-        for (int t = 0; t < kq; ++t) pw = cmulf(pw, u);
-        float bop[KS];
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int kk = 4 * ks + kq + 1;
-            bop[ks] = 0.0f;
-            if (ks < ksn) {
-                const float2 ak = (valid && kk <= q) ? As[kk] : make_float2(0.0f, 0.0f);
-                float2 t = cmulf(ak, pw);
-                if (kk & 1) { t.x = -t.x; t.y = -t.y; }
-                bop[ks] = comp ? t.y : t.x;
-                pw = cmulf(pw, u4);
+    const int32_t step = 8 * nw;
+    int32_t e = e0 + 8 * w;
+    if (e < e1) {
+        int32_t sb1 = (e + step + ps < e1) ? wl[e + step + ps] : 0;
+        m2l_chunk<KS, float2> cur;
+        m2l_fetch<KS, LOG, true>(a, bo, nbl, e, e1, (e + ps < e1) ? wl[e + ps] : 0, ps, kq, rmin, cur);
+        for (; e < e1; e += step) {
+            const int32_t en = e + step;
+            const int32_t sb2 = (en + step + ps < e1) ? wl[en + step + ps] : 0;
+            m2l_chunk<KS, float2> nxt;
+            m2l_fetch<KS, LOG, true>(a, bo, nbl, en, e1, sb1, ps, kq, rmin, nxt);
+            sb1 = sb2;
+
+            const bool valid = cur.valid;
+            const int qlim = valid ? cur.q : -1;
+            const int ksn = (cur.qc + 3) >> 2, mtn = (cur.qc >> 4) + 1;
+            const double2 r = make_double2(cur.cS.x - cT.x, cur.cS.y - cT.y);
+            double2 u64 = make_double2(0.0, 0.0), v64 = make_double2(0.0, 0.0);
+            if (valid) {
+                const double2 ri = cinv_fast(r);
+                u64 = make_double2(cur.sS * ri.x, cur.sS * ri.y);
+                v64 = make_double2(sT * ri.x, sT * ri.y);
             }
-        }
-        flt4 C[MT];
+            const float2 u1 = make_float2((float)u64.x, (float)u64.y);
+            const float2 v = make_float2((float)v64.x, (float)v64.y);
+            const float2 u2 = cmulf(u1, u1), u3 = cmulf(u2, u1), u4 = cmulf(u2, u2);
+            // as in the FP64 kernel, with u = sigma_S / r in place of 1/r
+            const float2 p0 = kq == 0 ? u1 : (kq == 1 ? u2 : (kq == 2 ? u3 : u4));
+            const float sg = (kq & 1) ? 1.0f : -1.0f;
+            float w1 = comp ? sg * p0.y : sg * p0.x;
+            float w2 = comp ? sg * p0.x : -sg * p0.y;
+            float bop[KS];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) C[mt] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                if (ks < ksn && mt < mtn)
-                    C[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
-        const double2 a064 = (valid && LOG) ? a.A[gS * P1] : make_double2(0.0, 0.0);
-        const float2 a0 = make_float2((float)a064.x, (float)a064.y);
-        const float2 v2 = cmulf(v, v), v4 = cmulf(v2, v2);
-        const float2 v16 = cmulf(cmulf(v4, v4), cmulf(v4, v4));
-        float2 base = make_float2(1.0f, 0.0f);
-        for (int t = 0; t < kq; ++t) base = cmulf(base, v4);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            if (mt >= mtn) break;
-            float2 pr = base;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = 16 * mt + 4 * kq + j;
-                const float mine = C[mt][j];
-                const float oth = dpp32<DPP_XOR1>(mine);
-                float2 Bl = comp ? make_float2(oth, mine) : make_float2(mine, oth);
-                if (LOG) {
-                    Bl.x -= a0.x * irow[mt][j];
-                    Bl.y -= a0.y * irow[mt][j];
+            for (int ks = 0; ks < KS; ++ks) {
+                bop[ks] = 0.0f;
+                if (ks < ksn) {
+                    const float2 ak = cur.ak[ks];
+                    bop[ks] = (4 * ks + kq + 1 <= qlim) ? fmaf(ak.y, w2, ak.x * w1) : 0.0f;
+                    const float t = fmaf(w2, u4.y, w1 * u4.x);
+                    w2 = fmaf(-w1, u4.y, w2 * u4.x);
+                    w1 = t;
                 }
-                const float2 res = cmulf(Bl, pr);
-                if (valid && row <= q) acc[mt][j] += comp ? res.y : res.x;
-                pr = cmulf(pr, v);
             }
-            base = cmulf(base, v16);
-        }
-        if (LOG && valid && kq == 0) {
-            const double2 lg = clog_principal(make_double2(cT.x - a.centre[2 * gS], cT.y - a.centre[2 * gS + 1]));
-            const double2 t = cmul(a064, lg);
-            acc0 += comp ? t.y : t.x;
+            flt4 C[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) C[mt] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    if (ks < ksn && mt < mtn)
+                        C[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
+            // post-scale with v = sigma_T / r: rows 16 mt + 4 kq + j
+            const float2 v2 = cmulf(v, v), v4 = cmulf(v2, v2), v8 = cmulf(v4, v4), v16 = cmulf(v8, v8);
+            const float2 b0 = kq == 0 ? make_float2(1.0f, 0.0f) : (kq == 1 ? v4 : (kq == 2 ? v8 : cmulf(v8, v4)));
+            const float sc = comp ? 1.0f : -1.0f;
+            const float d1 = sc * v.y, d16 = sc * v16.y;
+            float e1v = b0.x, e2v = sc * b0.y;
+            const float a0m = (float)(comp ? cur.a0.y : cur.a0.x), a0o = (float)(comp ? cur.a0.x : cur.a0.y);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                if (mt >= mtn) break;
+                float g1 = e1v, g2 = e2v;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = 16 * mt + 4 * kq + j;
+                    float mine = C[mt][j];
+                    float oth = dpp32<DPP_XOR1>(mine);
+                    if (LOG) {
+                        mine = fmaf(-a0m, irow[mt][j], mine);
+                        oth = fmaf(-a0o, irow[mt][j], oth);
+                    }
+                    const float res = fmaf(oth, g2, mine * g1);
+                    acc[mt][j] += (row <= qlim) ? res : 0.0f;
+                    const float t = fmaf(-g2, d1, g1 * v.x);
+                    g2 = fmaf(g1, d1, g2 * v.x);
+                    g1 = t;
+                }
+                const float t = fmaf(-e2v, d16, e1v * v16.x);
+                e2v = fmaf(e1v, d16, e2v * v16.x);
+                e1v = t;
+            }
+            if (LOG && valid && kq == 0) {
+                const double2 lg = clog_principal(make_double2(cT.x - cur.cS.x, cT.y - cur.cS.y));
+                const double2 t = cmul(cur.a0, lg);
+                acc0 += comp ? t.y : t.x;
+            }
+            cur = nxt;
         }
     }
 #pragma unroll
@@ -671,7 +752,7 @@ __device__ __forceinline__ double m2l32_unscale(double v, int row, double isT)
 // One launch: blocks [0, H) take the boxes with more than M2L_HEAVY weak pairs
 // (M2L_WAVES waves per box, fixed-order LDS reduction); the other blocks take
 // the light boxes, one wave per box.
-template <int MT, int KS>
+template <int MT, int KS, bool LOG>
 __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l32(m2l_args a, int32_t H)
 {
     __shared__ double part[M2L_WAVES][MT * 16][2];
@@ -687,7 +768,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l32(m2l_args a, int32_t H)
         if (m2l_range(a, g, l, e0, e1) > M2L_HEAVY) return;
         float acc[MT][4];
         double acc0;
-        m2l32_acc<MT, KS>(a, g, l, e0, e1, 0, 1, acc, acc0);
+        m2l32_acc<MT, KS, LOG>(a, g, l, e0, e1, 0, 1, acc, acc0);
         const double isT = 1.0 / scale_radius(a.radius[g], scale_floor(a.radius));
         double2 *Bt = a.B + g * P1;
 #pragma unroll
@@ -700,13 +781,17 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l32(m2l_args a, int32_t H)
                 if (ps == 0 && row <= a.p) reinterpret_cast<double *>(Bt + row)[comp] = m2l32_unscale(d, row, isT);
             }
     } else {
-        for (int64_t g = blockIdx.x; g < a.nb; g += H) {
+        // segments of the heavy boxes; partial sums (unscaled) go to hpart
+        const int32_t nseg = a.hoff[a.nb];
+        for (int32_t sg = blockIdx.x; sg < nseg; sg += H) {
+            const int64_t g = a.hbox[sg];
             int l;
             int32_t e0, e1;
-            if (m2l_range(a, g, l, e0, e1) <= M2L_HEAVY) continue;
+            m2l_range(a, g, l, e0, e1);
+            const int32_t s0 = min(e0 + (sg - a.hoff[g]) * M2L_SEG, e1), s1 = min(s0 + M2L_SEG, e1);
             float acc[MT][4];
             double acc0;
-            m2l32_acc<MT, KS>(a, g, l, e0, e1, w, M2L_WAVES, acc, acc0);
+            m2l32_acc<MT, KS, LOG>(a, g, l, s0, s1, w, M2L_WAVES, acc, acc0);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -719,7 +804,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l32(m2l_args a, int32_t H)
             __syncthreads();
             if (w == 0) {
                 const double isT = 1.0 / scale_radius(a.radius[g], scale_floor(a.radius));
-                double2 *Bt = a.B + g * P1;
+                double2 *Bt = a.hpart + (int64_t)sg * P1;
                 for (int k = lane; k < 2 * P1; k += WAVE) {
                     double v = 0.0;
                     for (int q = 0; q < M2L_WAVES; ++q) v += part[q][k >> 1][k & 1];
@@ -729,6 +814,44 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l32(m2l_args a, int32_t H)
             __syncthreads();
         }
     }
+}
+
+// Heavy-box segments: count per box, the box of every segment, and the
+// final sum of each heavy box's segment partials in segment order.
+__global__ void k_m2l_hcount(m2l_args a, int32_t *__restrict__ hs)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nb) return;
+    int l;
+    int32_t e0, e1;
+    const int32_t cnt = m2l_range(a, g, l, e0, e1);
+    hs[g] = cnt > M2L_HEAVY ? (cnt + M2L_SEG - 1) / M2L_SEG : 0;
+}
+
+__global__ void k_m2l_hfill(const int32_t *__restrict__ hs, const int32_t *__restrict__ hoff, int64_t nb,
+                            int32_t *__restrict__ hbox)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nb) return;
+    for (int32_t k = 0; k < hs[g]; ++k) hbox[hoff[g] + k] = (int32_t)g;
+}
+
+__global__ void k_m2l_hreduce(const int32_t *__restrict__ hs, const int32_t *__restrict__ hoff,
+                              const double2 *__restrict__ hpart, int P1, int64_t nb, double2 *__restrict__ B)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * P1) return;
+    const int64_t g = t / P1;
+    const int c = (int)(t - g * P1);
+    const int32_t n = hs[g];
+    if (n == 0) return;
+    double2 v = make_double2(0.0, 0.0);
+    for (int32_t k = 0; k < n; ++k) {
+        const double2 u = hpart[(int64_t)(hoff[g] + k) * P1 + c];
+        v.x += u.x;
+        v.y += u.y;
+    }
+    B[t] = v;
 }
 
 // FP32 radius-scaled copy of the multipoles: ahat_k = a_k / sigma^k.
@@ -821,8 +944,34 @@ static void launch_m2l(const m2l_args &m, bool mixed, hipStream_t st)
 {
     const int32_t H = (int32_t)(m.nb < 512 ? m.nb : 512);
     const unsigned nblk = (unsigned)(H + (m.nb + M2L_WAVES - 1) / M2L_WAVES);
-    if (mixed) k_m2l32<MT, KS><<<nblk, 64 * M2L_WAVES, 0, st>>>(m, H);
-    else k_m2l64<MT, KS><<<nblk, 64 * M2L_WAVES, 0, st>>>(m, H);
+    const bool LOG = m.kernel == FMM2D_KERNEL_LOG;
+    if (mixed) {
+        if (LOG) k_m2l32<MT, KS, true><<<nblk, 64 * M2L_WAVES, 0, st>>>(m, H);
+        else k_m2l32<MT, KS, false><<<nblk, 64 * M2L_WAVES, 0, st>>>(m, H);
+    } else {
+        if (LOG) k_m2l64<MT, KS, true><<<nblk, 64 * M2L_WAVES, 0, st>>>(m, H);
+        else k_m2l64<MT, KS, false><<<nblk, 64 * M2L_WAVES, 0, st>>>(m, H);
+    }
+}
+
+// Segments of the heavy boxes (after the lists, before the order phase,
+// whose sort works on the same units).
+hipError_t fmm_m2l_plan(const fmm_eval_args &a, hipStream_t st)
+{
+    const fmm_layout &lay = *a.lay;
+    m2l_args m;
+    memset(&m, 0, sizeof(m));
+    m.woff = WSC(int32_t, lay.woff);
+    m.nb = lay.nb;
+    m.L = a.L;
+    m.cap = (int32_t)lay.listcap;
+    int32_t *hs = WSC(int32_t, lay.hs), *hoff = WSC(int32_t, lay.hoff), *hbox = WSC(int32_t, lay.hbox);
+    const unsigned nbk = (unsigned)((lay.nb + 255) / 256);
+    k_m2l_hcount<<<nbk, 256, 0, st>>>(m, hs);
+    hipError_t e = fmm_scan_i32(hs, hoff, lay.nb, nullptr, WSC(int32_t, lay.bsum), st);
+    if (e != hipSuccess) return e;
+    k_m2l_hfill<<<nbk, 256, 0, st>>>(hs, hoff, lay.nb, hbox);
+    return hipGetLastError();
 }
 
 hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st)
@@ -844,6 +993,10 @@ hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st)
     m.p = a.p;
     m.kernel = a.kernel;
     m.cap = (int32_t)lay.listcap;
+    int32_t *hs = WSC(int32_t, lay.hs), *hoff = WSC(int32_t, lay.hoff), *hbox = WSC(int32_t, lay.hbox);
+    m.hoff = hoff;
+    m.hbox = hbox;
+    m.hpart = WSC(double2, lay.hpart);
     if (a.mixed) {
         const int64_t nt = lay.nb * (a.p + 1);
         k_scale_mpole<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(m.A, m.radius, WSC(float2, lay.A32),
@@ -857,5 +1010,7 @@ hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st)
     else if (MT <= 2 && KS <= 8) launch_m2l<2, 8>(m, a.mixed, st);
     else if (MT <= 3 && KS <= 12) launch_m2l<3, 12>(m, a.mixed, st);
     else launch_m2l<5, 16>(m, a.mixed, st);
+    const int64_t nc = lay.nb * (a.p + 1);
+    k_m2l_hreduce<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(hs, hoff, m.hpart, a.p + 1, lay.nb, m.B);
     return hipGetLastError();
 }

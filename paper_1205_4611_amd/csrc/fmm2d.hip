@@ -148,8 +148,16 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->tail = take(8 * lay->nb);
     lay->vmin = take(8 * lay->nb);
     lay->budget = take(8 * lay->nb);
+    // heavy-box segments: ceil(cnt / 512) <= cnt / 512 + 1 per box of more
+    // than 256 pairs, so at most listcap / 512 + listcap / 256 + 1 in total
+    lay->hmax = lay->listcap / 512 + lay->listcap / 256 + 1;
+    lay->hs = take(4 * (lay->nb + 1));
+    lay->hoff = take(4 * (lay->nb + 2));
+    lay->hbox = take(4 * lay->hmax);
+    lay->hpart = take(16 * lay->hmax * P1);
     lay->qw = learned ? take(lay->listcap) : 0;
     lay->sw = learned ? take(4 * lay->listcap) : 0;
+    lay->pbox = learned ? take(4 * lay->listcap) : 0;
     lay->sp = learned ? take(lay->listcap) : 0;
     lay->total = o;
     return 0;
@@ -264,6 +272,9 @@ static fmm_porder_args porder_args(fmm2d_handle *h, char *w, const fmm_layout &l
     a.radius = reinterpret_cast<const double *>(w + lay.radius);
     a.n1 = reinterpret_cast<const double *>(w + lay.n1);
     a.tail = reinterpret_cast<const double *>(w + lay.tail);
+    a.den = reinterpret_cast<double *>(w + lay.budget); // free outside the label computation
+    a.dpart = reinterpret_cast<double *>(w + lay.hpart);  // M2L partials are written later
+    a.pbox = lay.sw ? reinterpret_cast<int32_t *>(w + lay.pbox) : nullptr;
     a.woff = reinterpret_cast<const int32_t *>(w + lay.woff);
     a.widx = reinterpret_cast<const int32_t *>(w + lay.widx);
     a.p = p;
@@ -275,6 +286,9 @@ static fmm_porder_args porder_args(fmm2d_handle *h, char *w, const fmm_layout &l
     a.sw = lay.sw ? reinterpret_cast<int32_t *>(w + lay.sw) : nullptr;
     a.sp = lay.sp ? reinterpret_cast<uint8_t *>(w + lay.sp) : nullptr;
     a.status = h->d_status;
+    a.hoff = reinterpret_cast<const int32_t *>(w + lay.hoff);
+    a.hbox = reinterpret_cast<const int32_t *>(w + lay.hbox);
+    a.hmax = lay.hmax;
     return a;
 }
 
@@ -326,6 +340,7 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     ea.ns = n_src; ea.nt = nt ? nt : n_src; ea.at_sources = nt == 0;
     ea.ws = w; ea.lay = &lay; ea.binom = h->d_binom; ea.cap = cap; ea.swap = ta.swap;
     ea.porder = use_model || use_given;
+    HIPCHK(h, fmm_m2l_plan(ea, st));
     HIPCHK(h, fmm_p2m(ea, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], st));
     HIPCHK(h, fmm_m2m(ea, st));
@@ -397,6 +412,8 @@ extern "C" int fmm2d_sync(fmm2d_handle *h, void *stream)
         return fail(h, FMM2D_ENOSPC, "interaction lists overflowed list_cap; raise fmm2d_opts.list_cap");
     if (s & FMM_ST_ORDERS_SHORT)
         return fail(h, FMM2D_EINVAL, "the pair orders given are fewer than the weak pairs");
+    if (s & FMM_ST_TREE_INCONSISTENT)
+        return fail(h, FMM2D_EHIP, "internal error: inconsistent point lists in the tree build");
     return FMM2D_OK;
 }
 

@@ -29,6 +29,25 @@
 
 __device__ __forceinline__ float flog10(double v) { return (float)log10(fmax(v, 1e-300)); }
 
+// log10 of a positive FP64 value from its exact binary exponent and an FP32
+// log2 of the mantissa (absolute error ~1e-7); log10(0) = -inf.
+__device__ __forceinline__ float lg10_fast(double x)
+{
+    int e;
+    const double m = frexp(x, &e); // x = m 2^e, m in [0.5, 1)
+    return ((float)e + __log2f((float)m)) * 0.30102999566398120f;
+}
+// log10(max(a / b, 1e-300)) with b floored at 1e-300, as a difference of logs
+__device__ __forceinline__ float lg10_ratio(double a, double b)
+{
+    return fmaxf(lg10_fast(a) - lg10_fast(fmax(b, 1e-300)), -300.0f);
+}
+__device__ __forceinline__ double rcp_nr64(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 __device__ __forceinline__ int level_of_box(int64_t g, int L)
 {
     int l = 0;
@@ -71,16 +90,17 @@ __device__ __forceinline__ void pair_features(const feat_ctx &c, int64_t gS, flo
 {
     const double dx = c.centre[2 * c.g] - c.centre[2 * gS], dy = c.centre[2 * c.g + 1] - c.centre[2 * gS + 1];
     const double d = fmax(sqrt(dx * dx + dy * dy), 1e-300);
+    const double id = rcp_nr64(d);
     const double rS = c.radius[gS], rT = c.radius[c.g];
     const double nS = c.n1[gS];
-    f[0] = (float)(rS / d);
-    f[1] = (float)(rT / d);
-    f[2] = (float)((rS + rT) / d);
+    f[0] = (float)(rS * id);
+    f[1] = (float)(rT * id);
+    f[2] = (float)((rS + rT) * id);
     f[3] = c.L > 0 ? (float)((double)c.l / (double)c.L) : 0.0f;
-    f[4] = flog10(nS / fmax(c.n1root, 1e-300));
-    f[5] = flog10(c.tail[gS] / fmax(nS, 1e-300));
-    f[6] = flog10(nS / fmax(c.den, 1e-300));
-    f[7] = (float)log10((double)(c.nweak > 0 ? c.nweak : 1));
+    f[4] = lg10_ratio(nS, c.n1root);
+    f[5] = lg10_ratio(c.tail[gS], nS);
+    f[6] = lg10_ratio(nS, c.den);
+    f[7] = lg10_fast((double)(c.nweak > 0 ? c.nweak : 1));
 }
 
 // Shared set-up of the wave-per-target-box kernels: the box's weak range and
@@ -159,35 +179,158 @@ __global__ void __launch_bounds__(256) k_features(const double *__restrict__ cen
     }
 }
 
-// Orders of every weak pair (from the model, or the caller's array), written
-// in weak-list order to qw, then the box's pairs re-ordered by increasing
-// order (a stable counting sort with ballots) into sw (source box) and sp
-// (order), so that the M2L chunks of 8 consecutive pairs share similar
-// orders.
-__global__ void __launch_bounds__(256) k_porder(const double *__restrict__ centre, const double *__restrict__ radius,
-                                                const double *__restrict__ n1, const double *__restrict__ tail,
-                                                const int32_t *__restrict__ woff, const int32_t *__restrict__ widx,
-                                                const float *__restrict__ model, float delta,
-                                                const uint8_t *__restrict__ given, int64_t ngiven, int p, int L,
-                                                int64_t nb, int32_t cap, uint8_t *__restrict__ qw,
-                                                int32_t *__restrict__ sw, uint8_t *__restrict__ sp,
-                                                int32_t *__restrict__ status)
+// Orders of every weak pair (from the model, or the caller's array).  The
+// work is cut into the M2L work units (boxes of up to FMM_M2L_HEAVY weak pairs
+// and segments of FMM_M2L_SEG pairs of longer lists) so that very long lists
+// do not serialise:
+//   k_porder_units   one wave per unit: pair -> box map, share denominator
+//                    (partials of heavy boxes summed by k_porder_denred)
+//   k_porder_pairs   one thread per weak pair: features, MLP, order -> qw
+//   k_porder_sort    one wave per unit: the unit's pairs re-ordered by
+//                    increasing order (stable counting sort with ballots over
+//                    the unit's range of orders) into sw (source) and sp
+//                    (order), so that the M2L chunks of 8 pairs share similar
+//                    orders.
+#define PORDER_RCH 8 // chunks of 64 pairs per sort unit (FMM_M2L_SEG / 64)
+static_assert(PORDER_RCH * 64 >= FMM_M2L_SEG && PORDER_RCH * 64 >= FMM_M2L_HEAVY,
+              "a sort unit must fit the register window");
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+__device__ __forceinline__ bool box_range(const int32_t *__restrict__ woff, int L, int64_t g, int32_t cap,
+                                          int &l, int64_t &bo, int32_t &e0, int32_t &e1)
+{
+    l = level_of_box(g, L);
+    bo = d_box_off(l);
+    const int64_t so = d_start_off(l) + (g - bo);
+    e0 = min(woff[so], cap);
+    e1 = min(woff[so + 1], cap);
+    return e0 < e1;
+}
+
+// The M2L work units (a box of at most FMM_M2L_HEAVY weak pairs, or a segment
+// of FMM_M2L_SEG pairs of a longer list): unit t < nb is box t, unit nb + s is
+// heavy segment s.  Returns false for units that do not exist.
+__device__ __forceinline__ bool porder_unit(const int32_t *__restrict__ woff, const int32_t *__restrict__ hoff,
+                                            const int32_t *__restrict__ hbox, int L, int64_t nb, int32_t cap,
+                                            int64_t t, int64_t &g, int &l, int64_t &bo, int32_t &e0,
+                                            int32_t &e1)
+{
+    if (t < nb) {
+        g = t;
+    } else {
+        if (t - nb >= hoff[nb]) return false;
+        g = hbox[t - nb];
+    }
+    if (!box_range(woff, L, g, cap, l, bo, e0, e1)) return false;
+    if (e1 - e0 > FMM_M2L_HEAVY) {
+        if (t < nb) return false; // handled by its segments
+        const int32_t s0 = min(e0 + (int32_t)(t - nb - hoff[g]) * FMM_M2L_SEG, e1);
+        e1 = min(s0 + FMM_M2L_SEG, e1);
+        e0 = s0;
+    } else if (t >= nb) {
+        return false;
+    }
+    return true;
+}
+
+// Per unit: the pair -> target box map, and the unit's part of the share
+// denominator (the whole sum for a light box, a segment partial otherwise).
+__global__ void __launch_bounds__(256) k_porder_units(const double *__restrict__ n1, const int32_t *__restrict__ woff,
+                                                      const int32_t *__restrict__ widx,
+                                                      const int32_t *__restrict__ hoff,
+                                                      const int32_t *__restrict__ hbox, int L, int64_t nb,
+                                                      int32_t cap, int32_t *__restrict__ pbox,
+                                                      double *__restrict__ den, double *__restrict__ dpart)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t g = wave_index();
-    if (g >= nb) return;
-    int32_t e0, e1, nbl;
-    feat_ctx c;
-    if (!box_setup(centre, radius, n1, tail, woff, widx, L, g, cap, e0, e1, nbl, c)) return;
-    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
-    bool short_given = false;
+    const int64_t t = wave_index();
+    int64_t g, bo;
+    int l;
+    int32_t e0, e1;
+    if (!porder_unit(woff, hoff, hbox, L, nb, cap, t, g, l, bo, e0, e1)) {
+        if (t < nb && lane == 0) den[t] = 0.0; // heavy boxes are summed later; empty boxes 0
+        return;
+    }
+    const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
+    double s = 0.0;
     for (int32_t e = e0 + lane; e < e1; e += WAVE) {
+        s += n1[bo + min(max(widx[e], 0), nbl - 1)];
+        pbox[e] = (int32_t)g;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, WAVE);
+    if (lane == 0) {
+        if (t < nb) den[g] = s;
+        else dpart[t - nb] = s;
+    }
+}
+
+// Heavy boxes: the share denominator is the sum of the segment partials, in
+// segment order.
+__global__ void k_porder_denred(const int32_t *__restrict__ woff, const int32_t *__restrict__ hoff, int L,
+                                int64_t nb, int32_t cap, const double *__restrict__ dpart,
+                                double *__restrict__ den)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nb) return;
+    const int32_t n = hoff[g + 1] - hoff[g];
+    if (n == 0) return;
+    double s = 0.0;
+    for (int32_t k = 0; k < n; ++k) s += dpart[hoff[g] + k];
+    den[g] = s;
+}
+
+__global__ void __launch_bounds__(256) k_porder_pairs(const double *__restrict__ centre,
+                                                      const double *__restrict__ radius,
+                                                      const double *__restrict__ n1, const double *__restrict__ tail,
+                                                      const double *__restrict__ den,
+                                                      const int32_t *__restrict__ pbox,
+                                                      const int32_t *__restrict__ woff,
+                                                      const int32_t *__restrict__ widx,
+                                                      const float *__restrict__ model, float delta,
+                                                      const uint8_t *__restrict__ given, int64_t ngiven, int p,
+                                                      int L, int32_t cap, uint8_t *__restrict__ qw,
+                                                      int32_t *__restrict__ status)
+{
+    __shared__ float smodel[FMM2D_PORDER_MODEL_FLOATS];
+    if (model) {
+        for (int k = threadIdx.x; k < FMM2D_PORDER_MODEL_FLOATS; k += blockDim.x) smodel[k] = model[k];
+        __syncthreads();
+    }
+    const float *mw = model ? smodel : nullptr;
+    const int64_t nst = d_start_off(L + 1);
+    const int32_t npairs = min(woff[nst - 1], cap);
+    bool short_given = false;
+    for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < npairs; e += gridDim.x * blockDim.x) {
         int q = p;
-        if (model) {
+        if (mw) {
+            const int64_t g = pbox[e];
+            const int l = level_of_box(g, L);
+            const int64_t lo = d_start_off(l) + (g - d_box_off(l)); // entry of g in the offset arrays
+            const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
+            const int32_t s = widx[e];
+            feat_ctx c;
+            c.centre = centre; c.radius = radius; c.n1 = n1; c.tail = tail;
+            c.g = g; c.bo = d_box_off(l); c.l = l; c.L = L;
+            c.n1root = n1[0];
+            c.den = den[g];
+            c.nweak = woff[lo + 1] - woff[lo];
             float f[FMM_NF];
-            pair_features(c, c.bo + min(max(widx[e], 0), nbl - 1), f);
-            if (in_range(model, f)) {
-                const float y = mlp_eval(model, f) + delta;
+            pair_features(c, c.bo + min(max(s, 0), nbl - 1), f);
+            if (in_range(mw, f)) {
+                const float y = mlp_eval(mw, f) + delta;
                 const float yc = fminf(fmaxf(y, -1.0e6f), 1.0e6f); // NaN -> -1e6
                 const int qq = (int)ceilf(yc);
                 q = qq < FMM2D_PORDER_QMIN ? FMM2D_PORDER_QMIN : (qq > p ? p : qq);
@@ -202,31 +345,62 @@ __global__ void __launch_bounds__(256) k_porder(const double *__restrict__ centr
         }
         qw[e] = (uint8_t)q;
     }
-    if (__ballot(short_given) && lane == 0) atomicOr(status, FMM_ST_ORDERS_SHORT);
-    // the orders just stored are read back by other lanes of this wave
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    if (short_given) atomicOr(status, FMM_ST_ORDERS_SHORT);
+}
+
+// One wave per M2L work unit: a box of at most FMM_M2L_HEAVY weak pairs, or a
+// segment of FMM_M2L_SEG pairs of a longer list (units t < nb are boxes,
+// t - nb indexes the segments).  Within a unit the pairs are re-ordered by
+// increasing order; M2L only needs similar orders inside each chunk.
+__global__ void __launch_bounds__(256) k_porder_sort(const int32_t *__restrict__ woff,
+                                                     const int32_t *__restrict__ widx,
+                                                     const uint8_t *__restrict__ qw,
+                                                     const int32_t *__restrict__ hoff,
+                                                     const int32_t *__restrict__ hbox, int p, int L, int64_t nb,
+                                                     int32_t cap, int32_t *__restrict__ sw,
+                                                     uint8_t *__restrict__ sp)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t t = wave_index();
+    int64_t g, bo;
+    int l;
+    int32_t e0, e1;
+    if (!porder_unit(woff, hoff, hbox, L, nb, cap, t, g, l, bo, e0, e1)) return;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+    const int32_t nent = e1 - e0; // <= FMM_M2L_SEG = PORDER_RCH * 64
+    int qr[PORDER_RCH];
+    int32_t sr[PORDER_RCH];
+    int qlo = p + 1, qhi = 0;
+#pragma unroll
+    for (int k = 0; k < PORDER_RCH; ++k) {
+        const int32_t i = k * WAVE + lane;
+        qr[k] = 0; // 0 never matches an order
+        sr[k] = 0;
+        if (i < nent) {
+            qr[k] = qw[e0 + i];
+            sr[k] = widx[e0 + i];
+            qlo = min(qlo, qr[k]);
+            qhi = max(qhi, qr[k]);
+        }
+    }
+    qlo = wave_min_i(qlo);
+    qhi = wave_max_i(qhi);
+    const int32_t kmax = (nent + WAVE - 1) / WAVE;
     int32_t run = e0;
-    for (int qq = 1; qq <= p; ++qq) {
-        int32_t cnt = 0;
-        for (int32_t c0 = e0; c0 < e1; c0 += WAVE) {
-            const int32_t e = c0 + lane;
-            const int q = (e < e1) ? qw[e] : -1;
-            cnt += __popcll(__ballot(q == qq));
-        }
-        // scatter this order's pairs, stable in list order
-        int32_t base = run;
-        for (int32_t c0 = e0; c0 < e1 && cnt > 0; c0 += WAVE) {
-            const int32_t e = c0 + lane;
-            const int q = (e < e1) ? qw[e] : -1;
-            const uint64_t m = __ballot(q == qq);
-            if (q == qq) {
-                const int32_t dst = base + __popcll(m & lt);
-                sw[dst] = widx[e];
-                sp[dst] = (uint8_t)qq;
+    for (int qq = qlo; qq <= qhi; ++qq) {
+#pragma unroll
+        for (int k = 0; k < PORDER_RCH; ++k) {
+            if (k < kmax) {
+                const bool hit = qr[k] == qq;
+                const uint64_t m = __ballot(hit);
+                if (hit) {
+                    const int32_t dst = run + __popcll(m & lt);
+                    sw[dst] = sr[k];
+                    sp[dst] = (uint8_t)qq;
+                }
+                run += __popcll(m);
             }
-            base += __popcll(m);
         }
-        run += cnt;
     }
 }
 
@@ -487,9 +661,16 @@ hipError_t fmm_features(const fmm_porder_args &a, int64_t nfeat_cap, float *feat
 
 hipError_t fmm_porder(const fmm_porder_args &a, hipStream_t st)
 {
-    k_porder<<<(unsigned)((a.nb + 3) / 4), 256, 0, st>>>(a.centre, a.radius, a.n1, a.tail, a.woff, a.widx, a.model,
-                                                         a.delta, a.given, a.ngiven, a.p, a.L, a.nb, a.cap, a.qw, a.sw,
-                                                         a.sp, a.status);
+    const unsigned nub = (unsigned)((a.nb + a.hmax + 3) / 4); // units: boxes, then heavy-box segments
+    if (a.model) {
+        k_porder_units<<<nub, 256, 0, st>>>(a.n1, a.woff, a.widx, a.hoff, a.hbox, a.L, a.nb, a.cap, a.pbox, a.den,
+                                            a.dpart);
+        k_porder_denred<<<(unsigned)((a.nb + 255) / 256), 256, 0, st>>>(a.woff, a.hoff, a.L, a.nb, a.cap, a.dpart,
+                                                                         a.den);
+    }
+    k_porder_pairs<<<2048, 256, 0, st>>>(a.centre, a.radius, a.n1, a.tail, a.den, a.pbox, a.woff, a.widx, a.model,
+                                         a.delta, a.given, a.ngiven, a.p, a.L, a.cap, a.qw, a.status);
+    k_porder_sort<<<nub, 256, 0, st>>>(a.woff, a.widx, a.qw, a.hoff, a.hbox, a.p, a.L, a.nb, a.cap, a.sw, a.sp);
     return hipGetLastError();
 }
 

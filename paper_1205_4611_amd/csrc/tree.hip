@@ -496,16 +496,18 @@ __global__ void __launch_bounds__(SCAN_T) k_part_scatter(part_batch pb)
 // one workgroup takes a segment through all its remaining splits in LDS and
 // writes the box geometry, the per-level starts and the leaf order itself.
 // Local point ids are positions in the segment's (x, index)-ordered list; the
-// (y, index) order of the same points is rebuilt here by a bitonic sort, which
-// gives the same order as the global y list inside the segment.  The split
-// rules are those of the global steps (k_seg, rec_lo) evaluated in the same
-// arithmetic, so the tree is the same.
+// segment's (y, index)-ordered list is read too and mapped to local ids with
+// an LDS hash table of the original indices.  The split rules are those of
+// the global steps (k_seg, rec_lo) in the same arithmetic, so the tree is the
+// same.
 #define SUB_S 2048
 #define SUB_T 512
 #define SUB_I (SUB_S / SUB_T)
+#define SUB_HBITS 12                       // hash table of 4096 slots
+#define SUB_UNI 22544                      // step tables, or the hash table
 
 struct subtree_args {
-    const pt_rec *lx;           // x list after step k0
+    const pt_rec *lx, *ly;      // x and y lists after step k0
     const int32_t *sst;         // starts of the step-k0 segments (nseg0 + 1)
     int k0, L;
     int32_t nseg0;
@@ -513,56 +515,73 @@ struct subtree_args {
     double *centre, *radius;    // all levels
     int32_t *sstart;            // per-level starts, all levels
     int32_t *perm;
+    int32_t *status;
 };
+
+__device__ __forceinline__ uint32_t sub_hash(int32_t idx)
+{
+    return ((uint32_t)idx * 2654435761u) >> (32 - SUB_HBITS);
+}
 
 __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
 {
     __shared__ double px[SUB_S], py[SUB_S];
     __shared__ int32_t pid[SUB_S];
     __shared__ uint16_t lst[2][2][SUB_S]; // [buffer][x or y list][position] -> local id
-    __shared__ uint16_t st[2][SUB_S + 1]; // [buffer] sub-segment starts
-    __shared__ uint16_t piv[SUB_S];       // pivot local id per sub-segment
-    __shared__ uint8_t axs[SUB_S];
-    __shared__ uint16_t exs[2][SUB_S];    // exclusive scans of the lo flags
+    __shared__ __align__(16) unsigned char uni[SUB_UNI];
     __shared__ int32_t sh[SUB_T / WAVE];
+    // step tables (after set-up) ...
+    uint16_t(*st)[SUB_S + 1] = reinterpret_cast<uint16_t(*)[SUB_S + 1]>(uni); // 8196 B
+    uint16_t *piv = reinterpret_cast<uint16_t *>(uni + 8200);                  // 4096 B
+    uint8_t *axs = uni + 12296;                                                // 2048 B
+    uint16_t(*exs)[SUB_S] = reinterpret_cast<uint16_t(*)[SUB_S]>(uni + 14344); // 8192 B
+    // ... or the hash table during set-up: local id per slot, -1 = empty
+    int32_t *hsh = reinterpret_cast<int32_t *>(uni);                           // 16384 B
     const int tid = threadIdx.x;
     const int32_t g0 = blockIdx.x;
     const int32_t base = a.sst[g0];
     const int32_t n = min(max(a.sst[g0 + 1] - base, 0), SUB_S);
+    for (int i = tid; i < (1 << SUB_HBITS); i += SUB_T) hsh[i] = -1;
     for (int i = tid; i < n; i += SUB_T) {
         const pt_rec r = a.lx[base + i];
         px[i] = r.x;
         py[i] = r.y;
         pid[i] = r.idx;
-    }
-    for (int i = tid; i < SUB_S; i += SUB_T) {
         lst[0][0][i] = (uint16_t)i;
-        lst[0][1][i] = (uint16_t)i;
     }
+    __syncthreads();
+    // local id of every original index (linear probing; at most n < 4096 occupied)
+    for (int i = tid; i < n; i += SUB_T) {
+        uint32_t h = sub_hash(pid[i]);
+        for (int probe = 0; probe < (1 << SUB_HBITS); ++probe) {
+            if (atomicCAS(&hsh[h], -1, i) == -1) break;
+            h = (h + 1) & ((1u << SUB_HBITS) - 1);
+        }
+    }
+    __syncthreads();
+    // the y list of the same points, as local ids (every index is present;
+    // the probe count is bounded all the same)
+    bool missing = false;
+    for (int i = tid; i < n; i += SUB_T) {
+        const int32_t idx = a.ly[base + i].idx;
+        uint32_t h = sub_hash(idx);
+        int32_t id = -1;
+        for (int probe = 0; probe < (1 << SUB_HBITS); ++probe) {
+            const int32_t c = hsh[h];
+            if (c < 0) break;
+            if (pid[c] == idx) { id = c; break; }
+            h = (h + 1) & ((1u << SUB_HBITS) - 1);
+        }
+        missing = missing || id < 0;
+        lst[0][1][i] = (uint16_t)(id < 0 ? 0 : id);
+    }
+    if (missing) atomicOr(a.status, FMM_ST_TREE_INCONSISTENT);
+    __syncthreads();
     if (tid == 0) {
         st[0][0] = 0;
         st[0][1] = (uint16_t)n;
     }
     __syncthreads();
-    // (y, index) order: bitonic sort of the local ids; ids >= n sort last
-    for (int k = 2; k <= SUB_S; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < SUB_S; i += SUB_T) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint16_t u = lst[0][1][i], v = lst[0][1][l];
-                    bool gt; // key(u) > key(v)
-                    if (u >= n || v >= n) gt = u >= n && (v < n || u > v);
-                    else gt = py[u] > py[v] || (py[u] == py[v] && pid[u] > pid[v]);
-                    if (((i & k) == 0) == gt) {
-                        lst[0][1][i] = v;
-                        lst[0][1][l] = u;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
     const int J = 2 * a.L - a.k0;
     int cur = 0;
     for (int j = 0; j <= J; ++j) {
@@ -660,7 +679,11 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
         __syncthreads();
         cur = nxt;
     }
-    // (d) leaf order: inside every leaf the sources by ascending original index
+    // (d) leaf order: inside every leaf the sources by ascending original
+    // index (px is free now: it holds the original index of each final position)
+    int32_t *pidl = reinterpret_cast<int32_t *>(px);
+    for (int p = tid; p < n; p += SUB_T) pidl[p] = pid[lst[cur][0][p]];
+    __syncthreads();
     const int32_t nleaf = 1 << J;
     for (int p = tid; p < n; p += SUB_T) {
         int32_t lo_t = 0, hi_t = nleaf - 1;
@@ -669,9 +692,9 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
             if (st[cur][mid] <= p) lo_t = mid; else hi_t = mid - 1;
         }
         const int32_t s0 = st[cur][lo_t], s1 = st[cur][lo_t + 1];
-        const int32_t me = pid[lst[cur][0][p]];
+        const int32_t me = pidl[p];
         int32_t r = 0;
-        for (int32_t k = s0; k < s1; ++k) r += pid[lst[cur][0][k]] < me;
+        for (int32_t k = s0; k < s1; ++k) r += pidl[k] < me;
         a.perm[base + s0 + min(r, s1 - s0 - 1)] = me;
     }
 }
@@ -903,6 +926,8 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         if (k == k0) {
             subtree_args ta;
             ta.lx = sl[0];
+            ta.ly = sl[1];
+            ta.status = a.status;
             ta.sst = sstep + soff_k;
             ta.k0 = k0;
             ta.L = L;
