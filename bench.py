@@ -142,7 +142,7 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override N (default 2^22)")
     ap.add_argument("--p", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--paths", default="headline,fp64,far32,mixed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES bytes (counter calibration)")
