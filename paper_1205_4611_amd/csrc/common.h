@@ -73,6 +73,8 @@ struct fmm_layout {
     size_t n1, tail;             // per-box coefficient norms (order features)
     size_t vmin, budget;         // per-box label budget
     size_t hs, hoff, hbox, hpart; // M2L heavy-box segments (counts, offsets, box, partials)
+    size_t nhw, nhoff, nuleaf, npart; // near-field units of heavy leaves
+    int64_t nucap;               // capacity in near-field units
     int64_t hmax;                // capacity in segments
     size_t qw;                   // uint8 order per weak pair, weak-list order
     size_t sw, sp;               // weak pairs sorted by order within a box: source, order
@@ -121,6 +123,7 @@ hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st);
 #define FMM_M2L_SEG 512    // pairs per segment
 hipError_t fmm_l2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_p2l(const fmm_eval_args &a, hipStream_t st);
+hipError_t fmm_near_plan(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_p2p_l2p(const fmm_eval_args &a, double *phi, double *dphi, hipStream_t st);
 
 // learned / given per-pair orders (porder.hip)

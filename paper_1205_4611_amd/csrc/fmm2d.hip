@@ -155,6 +155,13 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->hoff = take(4 * (lay->nb + 2));
     lay->hbox = take(4 * lay->hmax);
     lay->hpart = take(16 * lay->hmax * P1);
+    // near-field units of heavy leaves: about one per leaf (heavy leaves past
+    // the capacity are evaluated whole)
+    lay->nucap = lay->nleaf + 1024;
+    lay->nhw = take(4 * (lay->nleaf + 1));
+    lay->nhoff = take(4 * (lay->nleaf + 2));
+    lay->nuleaf = take(4 * lay->nucap);
+    lay->npart = take(8 * 4 * 64 * lay->nucap);
     lay->qw = learned ? take(lay->listcap) : 0;
     lay->sw = learned ? take(4 * lay->listcap) : 0;
     lay->pbox = learned ? take(4 * lay->listcap) : 0;
@@ -341,6 +348,7 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     ea.ws = w; ea.lay = &lay; ea.binom = h->d_binom; ea.cap = cap; ea.swap = ta.swap;
     ea.porder = use_model || use_given;
     HIPCHK(h, fmm_m2l_plan(ea, st));
+    HIPCHK(h, fmm_near_plan(ea, st));
     HIPCHK(h, fmm_p2m(ea, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], st));
     HIPCHK(h, fmm_m2m(ea, st));
