@@ -188,6 +188,11 @@ __global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t *__restrict__ k
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one pass.  The block's 4096 elements get their stable rank
+// within their digit (16 sub-tiles of 256 in order, peers of a digit found by
+// ballots over its 8 bits), are staged in LDS in digit order, and are then
+// written out so that consecutive threads write consecutive addresses of a
+// digit's run.
 __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict__ kin,
                                                       const int32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout,
@@ -195,45 +200,70 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
                                                       int shift, const int32_t *__restrict__ off,
                                                       int nblk)
 {
-    __shared__ int32_t run[256];
+    __shared__ uint64_t sk[RS_BLOCK];
+    __shared__ int32_t sv[RS_BLOCK];
+    __shared__ int32_t cnt[256];
+    __shared__ int32_t dstart[256];
     __shared__ int32_t wc[RS_T / WAVE][256];
+    __shared__ int32_t sh[RS_T / WAVE];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-    run[tid] = off[(int64_t)tid * nblk + blockIdx.x];
+    cnt[tid] = 0;
     for (int q = 0; q < RS_T / WAVE; ++q) wc[q][tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_BLOCK;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+    uint64_t key[RS_TILES];
+    int32_t val[RS_TILES], rk[RS_TILES];
+#pragma unroll
     for (int t = 0; t < RS_TILES; ++t) {
-        int64_t k = base + (int64_t)t * RS_T + tid;
-        bool valid = k < n;
-        uint64_t key = valid ? kin[k] : 0ull;
-        int d = (int)((key >> shift) & 255);
+        const int64_t k = base + (int64_t)t * RS_T + tid;
+        const bool valid = k < n;
+        key[t] = valid ? kin[k] : 0ull;
+        val[t] = valid ? vin[k] : 0;
+        const int d = (int)((key[t] >> shift) & 255);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            bool bit = (d >> b) & 1;
-            uint64_t bb = __ballot(bit);
+            const bool bit = (d >> b) & 1;
+            const uint64_t bb = __ballot(bit);
             peers &= bit ? bb : ~bb;
         }
-        int rank = __popcll(peers & lt);
-        bool leader = valid && rank == 0;
-        if (leader) wc[w][d] = __popcll(peers);
+        const int rank = __popcll(peers & lt);
+        if (valid && rank == 0) wc[w][d] = __popcll(peers);
         __syncthreads();
-        if (valid) {
-            int64_t pos = run[d] + rank;
-            for (int q = 0; q < w; ++q) pos += wc[q][d];
-            pos = pos < 0 ? 0 : (pos >= n ? n - 1 : pos); // never leave the array
-            kout[pos] = key;
-            vout[pos] = vin[k];
-        }
+        int32_t r = cnt[d] + rank;
+        for (int q = 0; q < w; ++q) r += wc[q][d];
+        rk[t] = valid ? r : -1;
         __syncthreads();
         int32_t add = 0;
         for (int q = 0; q < RS_T / WAVE; ++q) {
             add += wc[q][tid];
             wc[q][tid] = 0;
         }
-        run[tid] += add;
+        cnt[tid] += add;
         __syncthreads();
+    }
+    int32_t tot;
+    dstart[tid] = block_excl_scan(cnt[tid], sh, &tot);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RS_TILES; ++t) {
+        if (rk[t] >= 0) {
+            const int d = (int)((key[t] >> shift) & 255);
+            const int p = min(dstart[d] + rk[t], RS_BLOCK - 1);
+            sk[p] = key[t];
+            sv[p] = val[t];
+        }
+    }
+    __syncthreads();
+    const int nvalid = (int)min((int64_t)RS_BLOCK, n - base);
+    for (int j = tid; j < nvalid; j += RS_T) {
+        const uint64_t kk = sk[j];
+        const int d = (int)((kk >> shift) & 255);
+        int64_t pos = (int64_t)off[(int64_t)d * nblk + blockIdx.x] + (j - dstart[d]);
+        pos = pos < 0 ? 0 : (pos >= n ? n - 1 : pos); // never leave the array
+        kout[pos] = kk;
+        vout[pos] = sv[j];
     }
 }
 
