@@ -84,6 +84,24 @@ __device__ __forceinline__ double sum8_64(double v)
     v += dpp64<DPP_ROR8>(v);
     return v;
 }
+// Sum and largest value over the 16 lanes of a row (the 16 pairs of an FP64
+// M2L chunk): xor 1, xor 2, then rotations by 4 and 8.
+__device__ __forceinline__ double sum16_64(double v)
+{
+    v += dpp64<DPP_XOR1>(v);
+    v += dpp64<DPP_XOR2>(v);
+    v += dpp64<DPP_ROR4>(v);
+    v += dpp64<DPP_ROR8>(v);
+    return v;
+}
+__device__ __forceinline__ int max16_i(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_XOR1, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_XOR2, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_ROR4, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_ROR8, 0xF, 0xF, false));
+    return v;
+}
 // Largest value over the same 8 lanes (the pairs of a chunk).
 __device__ __forceinline__ int max8_i(int v)
 {
@@ -407,141 +425,199 @@ __device__ __forceinline__ void m2l_fetch(const m2l_args &a, int64_t bo, int32_t
     c.sS = F32 ? scale_radius(a.radius[gS], rmin) : 0.0;
 }
 
-// FP64 contraction for the chunks c = w, w + nw, ... of 8 weak pairs of box g.
-// Lane layout of v_mfma_f64_16x16x4f64: A operand lane i holds A[i%16][i/16],
-// B operand lane i holds B[i/16][i%16], accumulator element j of lane i holds
-// row 4j + i/16 of column i%16 (the FP64 instruction interleaves its rows).
-// On return acc[mt][j] holds, summed over this lane's pairs, the re (even
-// column) or im (odd column) part of b_l, l = 16 mt + 4 j + kq.
+// Operands of one chunk of 16 weak pairs for the FP64 contraction: lane
+// (pr, kq) = (lane % 16, lane / 16) holds pair pr's source centre and its
+// coefficients a_k, k = 4 ks + kq + 1, as full complex numbers; terms above
+// the pair's order q are loaded as zero.
+template <int KS>
+struct m2l_chunk16 {
+    double2 cS;
+    double2 ak[KS];
+    double2 a0; // a_0 (log kernel)
+    int q, qc;  // this pair's order, the chunk's largest order
+    bool valid;
+};
+
+template <int KS, bool LOG>
+__device__ __forceinline__ void m2l_fetch16(const m2l_args &a, int64_t bo, int32_t nbl, int32_t e, int32_t e1,
+                                            int32_t sbraw, int pr, int kq, m2l_chunk16<KS> &c)
+{
+    const int p = a.p, P1 = p + 1;
+    const int32_t pe = e + pr;
+    c.valid = pe < e1;
+    const int32_t sb = min(max(c.valid ? sbraw : 0, 0), nbl - 1);
+    const int64_t gS = bo + sb;
+    c.cS = make_double2(a.centre[2 * gS], a.centre[2 * gS + 1]);
+    c.q = c.valid ? p : -1;
+    c.qc = p;
+    if (a.sp) {
+        c.q = c.valid ? (int)a.sp[pe] : -1;
+        // the chunk's largest order bounds its k-steps and row tiles
+        c.qc = __builtin_amdgcn_readfirstlane(max16_i(c.q));
+    }
+    const double2 *As = a.A + gS * P1;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int kk = 4 * ks + kq + 1;
+        c.ak[ks] = (kk <= c.q) ? As[kk] : make_double2(0.0, 0.0);
+    }
+    c.a0 = (LOG && c.valid) ? As[0] : make_double2(0.0, 0.0);
+}
+
+// One chunk of 16 weak pairs in FP64 with MTN row tiles and KSN k-steps
+// (the chunk's largest order qc needs rows 0..qc and a_1..a_qc).  Lane layout
+// of v_mfma_f64_16x16x4f64: A operand lane i holds A[i%16][i/16], B operand
+// lane i holds B[i/16][i%16], accumulator element j of lane i holds row
+// 4j + i/16 of column i%16.  Columns are pairs; the real and imaginary parts
+// of the scaled coefficients go through two accumulators, so every lane holds
+// whole complex numbers of its pair and needs no lane exchange before the
+// post-scaling.  Straight-line code for each (MTN, KSN): the accumulators are
+// never merged across skipped products.
+template <int MT, int KS, int MTN, int KSN, bool LOG>
+__device__ __forceinline__ void m2l64_chunk(const double *Sl, const double *Il, const m2l_chunk16<KS> &c,
+                                            double2 cT, int kq, double (&re)[MT][4], double (&im)[MT][4])
+{
+    const int qlim = c.q; // rows above the pair's order are dropped (-1: no pair)
+    const double2 r = make_double2(c.cS.x - cT.x, c.cS.y - cT.y);
+    const double2 r1 = c.valid ? cinv_fast(r) : make_double2(0.0, 0.0);
+    const double2 r2 = cmul(r1, r1), r3 = cmul(r2, r1), r4 = cmul(r2, r2);
+    // Pre-scale: beta_{k'} = (-1)^{k'+1} a_{k'+1} r^{-(k'+1)}, k' = 4 ks + kq;
+    // the power advances by r^-4 per k-step (an even power: no sign change).
+    const double2 p0 = kq == 0 ? r1 : (kq == 1 ? r2 : (kq == 2 ? r3 : r4)); // r^{-(kq+1)}
+    const double sg = (kq & 1) ? 1.0 : -1.0;                                // (-1)^{kq+1}
+    double2 W = make_double2(sg * p0.x, sg * p0.y);
+    double bre[KSN], bim[KSN];
+#pragma unroll
+    for (int ks = 0; ks < KSN; ++ks) {
+        const double2 ak = c.ak[ks];
+        bre[ks] = fma(-ak.y, W.y, ak.x * W.x);
+        bim[ks] = fma(ak.y, W.x, ak.x * W.y);
+        if (ks + 1 < KSN) W = cmul(W, r4);
+    }
+    dbl4 Cr[MTN], Ci[MTN];
+#pragma unroll
+    for (int mt = 0; mt < MTN; ++mt) {
+        const double sv = Sl[16 * mt * (4 * KS)];
+        Cr[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, bre[0], dbl4{0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
+        Ci[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, bim[0], dbl4{0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
+    }
+#pragma unroll
+    for (int ks = 1; ks < KSN; ++ks)
+#pragma unroll
+        for (int mt = 0; mt < MTN; ++mt) {
+            const double sv = Sl[16 * mt * (4 * KS) + 4 * ks];
+            Cr[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, bre[ks], Cr[mt], 0, 0, 0);
+            Ci[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, bim[ks], Ci[mt], 0, 0, 0);
+        }
+    // Post-scale: row l = 16 mt + 4 j + kq gets r^{-l} (B_l - a_0/l); the
+    // power starts at r^{-kq} and advances by r^-4 per row, r^-16 per tile.
+    double2 u = kq == 0 ? make_double2(1.0, 0.0) : (kq == 1 ? r1 : (kq == 2 ? r2 : r3)); // r^{-kq}
+#pragma unroll
+    for (int mt = 0; mt < MTN; ++mt) {
+        double2 v = u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = 16 * mt + 4 * j + kq;
+            double cr = Cr[mt][j], ci = Ci[mt][j];
+            if (LOG) {
+                const double il = Il[16 * mt + 4 * j]; // 1/l (0 for l = 0)
+                cr = fma(-c.a0.x, il, cr);
+                ci = fma(-c.a0.y, il, ci);
+            }
+            const double f = (row <= qlim) ? 1.0 : 0.0;
+            re[mt][j] = fma(f, fma(-ci, v.y, cr * v.x), re[mt][j]);
+            im[mt][j] = fma(f, fma(ci, v.x, cr * v.y), im[mt][j]);
+            if (j < 3) v = cmul(v, r4);
+        }
+        if (mt + 1 < MTN) u = cmul(u, cmul(cmul(r4, r4), cmul(r4, r4)));
+    }
+    if (LOG && c.valid && kq == 0) {
+        // Log(c_T - c_S), the difference formed as written: on the branch
+        // cut the sign of a zero imaginary part decides between +pi and -pi
+        const double2 lg = clog_principal(make_double2(cT.x - c.cS.x, cT.y - c.cS.y));
+        const double2 t = cmul(c.a0, lg);
+        re[0][0] += t.x;
+        im[0][0] += t.y;
+    }
+}
+
+// Chooses the straight-line body for the chunk's (mtn, ksn): the full one
+// first (fixed orders), then the combinations a largest order can give
+// (mtn tiles need 4 (mtn - 1) <= ksn <= 4 mtn k-steps).  The full body is
+// correct for every chunk (terms above a pair's order are zero or masked),
+// so it is also the fallback.
+template <int MT, int KS, bool LOG, int MTN, int KSN>
+__device__ __forceinline__ void m2l64_pick(int mtn, int ksn, const double *Sl, const double *Il,
+                                           const m2l_chunk16<KS> &c, double2 cT, int kq, double (&re)[MT][4],
+                                           double (&im)[MT][4])
+{
+    constexpr bool legal = KSN >= (MTN > 1 ? 4 * (MTN - 1) : 1) && KSN <= 4 * MTN;
+    if constexpr (MTN == 0) {
+        m2l64_chunk<MT, KS, MT, KS, LOG>(Sl, Il, c, cT, kq, re, im);
+    } else if constexpr (!legal || (MTN == MT && KSN == KS)) {
+        if constexpr (KSN > 1) m2l64_pick<MT, KS, LOG, MTN, KSN - 1>(mtn, ksn, Sl, Il, c, cT, kq, re, im);
+        else m2l64_pick<MT, KS, LOG, MTN - 1, KS>(mtn, ksn, Sl, Il, c, cT, kq, re, im);
+    } else {
+        if (mtn == MTN && ksn == KSN) {
+            m2l64_chunk<MT, KS, MTN, KSN, LOG>(Sl, Il, c, cT, kq, re, im);
+        } else if constexpr (KSN > 1) {
+            m2l64_pick<MT, KS, LOG, MTN, KSN - 1>(mtn, ksn, Sl, Il, c, cT, kq, re, im);
+        } else {
+            m2l64_pick<MT, KS, LOG, MTN - 1, KS>(mtn, ksn, Sl, Il, c, cT, kq, re, im);
+        }
+    }
+}
+
+// FP64 contraction for the chunks c = w, w + nw, ... of 16 weak pairs of box
+// g.  On return (re, im)[mt][j] hold b_l, l = 16 mt + 4 j + kq, summed over
+// the chunks' pairs (lane kq = lane / 16).
 template <int MT, int KS, bool LOG>
-__device__ __forceinline__ void m2l64_acc(const m2l_args &a, int64_t g, int l, int32_t e0, int32_t e1, int w,
-                                          int nw, double (&acc)[MT][4])
+__device__ __forceinline__ void m2l64_acc(const m2l_args &a, const double *Sop, int64_t g, int l, int32_t e0,
+                                          int32_t e1, int w, int nw, double (&re)[MT][4], double (&im)[MT][4])
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t bo = d_box_off(l);
-    const int p = a.p;
-    const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
+    const int pr = lane & 15, kq = lane >> 4;
     const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
     const double2 cT = make_double2(a.centre[2 * g], a.centre[2 * g + 1]);
-    double Sop[MT][KS];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int row = 16 * mt + col, kk = 4 * ks + kq;
-            Sop[mt][ks] = (row <= p && kk < p) ? a.binom[(row + kk) * FMM_BN + row] : 0.0;
-        }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
-    // 1/l for the a_0 term of the rows this lane holds (log kernel)
-    double irow[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int row = 16 * mt + 4 * j + kq;
-            irow[mt][j] = (LOG && row >= 1) ? 1.0 / row : 0.0;
+            re[mt][j] = 0.0;
+            im[mt][j] = 0.0;
         }
+    // this lane's A operands S[16 mt + pr][4 ks + kq] and 1/l for its rows,
+    // read from the block's tables
+    const double *Sl = Sop + pr * (4 * KS) + kq;
+    const double *Il = Sop + MT * 16 * 4 * KS + kq;
     const int32_t *wl = a.sw ? a.sw : a.widx;
-    const int32_t step = 8 * nw;
-    int32_t e = e0 + 8 * w;
+    const int32_t step = 16 * nw;
+    int32_t e = e0 + 16 * w;
     if (e < e1) {
-        int32_t sb1 = (e + step + ps < e1) ? wl[e + step + ps] : 0;
-        m2l_chunk<KS, double2> cur;
-        m2l_fetch<KS, LOG, false>(a, bo, nbl, e, e1, (e + ps < e1) ? wl[e + ps] : 0, ps, kq, 0.0, cur);
+        int32_t sb1 = (e + step + pr < e1) ? wl[e + step + pr] : 0;
+        m2l_chunk16<KS> cur;
+        m2l_fetch16<KS, LOG>(a, bo, nbl, e, e1, (e + pr < e1) ? wl[e + pr] : 0, pr, kq, cur);
         for (; e < e1; e += step) {
             // prefetch: the list entry two chunks ahead, the operands of the next
             const int32_t en = e + step;
-            const int32_t sb2 = (en + step + ps < e1) ? wl[en + step + ps] : 0;
-            m2l_chunk<KS, double2> nxt;
-            m2l_fetch<KS, LOG, false>(a, bo, nbl, en, e1, sb1, ps, kq, 0.0, nxt);
+            const int32_t sb2 = (en + step + pr < e1) ? wl[en + step + pr] : 0;
+            m2l_chunk16<KS> nxt;
+            m2l_fetch16<KS, LOG>(a, bo, nbl, en, e1, sb1, pr, kq, nxt);
             sb1 = sb2;
-
-            const bool valid = cur.valid;
-            const int qlim = valid ? cur.q : -1; // rows and k-terms above this order are dropped
-            const int ksn = (cur.qc + 3) >> 2, mtn = (cur.qc >> 4) + 1;
-            const double2 r = make_double2(cur.cS.x - cT.x, cur.cS.y - cT.y);
-            const double2 r1 = valid ? cinv_fast(r) : make_double2(0.0, 0.0);
-            const double2 r2 = cmul(r1, r1), r3 = cmul(r2, r1), r4 = cmul(r2, r2);
-            // This lane needs one component (comp) of complex products only.
-            // Pre-scale: bop[ks] = comp part of (-1)^{k'+1} a_{k'+1} r^{-(k'+1)},
-            // k' = 4 ks + kq, written as a.x w1 + a.y w2; multiplying the power
-            // by r^-4 maps (w1, w2) -> (w1 c + w2 d, w2 c - w1 d), r^-4 = c + i d.
-            const double2 p0 = kq == 0 ? r1 : (kq == 1 ? r2 : (kq == 2 ? r3 : r4)); // r^{-(kq+1)}
-            const double sg = (kq & 1) ? 1.0 : -1.0;                                // (-1)^{kq+1}
-            double w1 = comp ? sg * p0.y : sg * p0.x;
-            double w2 = comp ? sg * p0.x : -sg * p0.y;
-            double bop[KS];
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                bop[ks] = 0.0;
-                if (ks < ksn) {
-                    const double2 ak = cur.ak[ks];
-                    bop[ks] = (4 * ks + kq + 1 <= qlim) ? fma(ak.y, w2, ak.x * w1) : 0.0;
-                    const double t = fma(w2, r4.y, w1 * r4.x);
-                    w2 = fma(-w1, r4.y, w2 * r4.x);
-                    w1 = t;
-                }
-            }
-            dbl4 C[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) C[mt] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                    if (ks < ksn && mt < mtn)
-                        C[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Sop[mt][ks], bop[ks], C[mt], 0, 0, 0);
-            // Post-scale: row l = 16 mt + 4 j + kq gets r^{-l} (B_l - a_0/l);
-            // with (mine, oth) the lane's and the other component of B_l, the
-            // lane's part is mine v1 + oth v2, (v1, v2) = (Re, +-Im) of r^{-l}.
-            const double2 b0 = kq == 0 ? make_double2(1.0, 0.0) : (kq == 1 ? r1 : (kq == 2 ? r2 : r3)); // r^{-kq}
-            const double sc = comp ? 1.0 : -1.0;
-            const double d4 = sc * r4.y;
-            const double2 r8 = cmul(r4, r4), r16 = cmul(r8, r8);
-            const double d16 = sc * r16.y;
-            double u1 = b0.x, u2 = sc * b0.y;
-            const double a0m = comp ? cur.a0.y : cur.a0.x, a0o = comp ? cur.a0.x : cur.a0.y;
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                if (mt >= mtn) break;
-                double v1 = u1, v2 = u2;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int row = 16 * mt + 4 * j + kq;
-                    double mine = C[mt][j];
-                    double oth = dpp64<DPP_XOR1>(mine);
-                    if (LOG) {
-                        mine = fma(-a0m, irow[mt][j], mine);
-                        oth = fma(-a0o, irow[mt][j], oth);
-                    }
-                    const double res = fma(oth, v2, mine * v1);
-                    acc[mt][j] += (row <= qlim) ? res : 0.0;
-                    const double t = fma(-v2, d4, v1 * r4.x);
-                    v2 = fma(v1, d4, v2 * r4.x);
-                    v1 = t;
-                }
-                const double t = fma(-u2, d16, u1 * r16.x);
-                u2 = fma(u1, d16, u2 * r16.x);
-                u1 = t;
-            }
-            if (LOG && valid && kq == 0) {
-                // Log(c_T - c_S), the difference formed as written: on the branch
-                // cut the sign of a zero imaginary part decides between +pi and -pi
-                const double2 lg = clog_principal(make_double2(cT.x - cur.cS.x, cT.y - cur.cS.y));
-                const double2 t = cmul(cur.a0, lg);
-                acc[0][0] += comp ? t.y : t.x;
-            }
+            const int ksn = min(max((cur.qc + 3) >> 2, 1), KS), mtn = min((cur.qc >> 4) + 1, MT);
+            m2l64_pick<MT, KS, LOG, MT, KS>(mtn, ksn, Sl, Il, cur, cT, kq, re, im);
             cur = nxt;
         }
     }
-    // sum over the 8 pairs of a tile (lane bits 1..3)
+    // sum over the 16 pairs of a tile (lane bits 0..3)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[mt][j] = sum8_64(acc[mt][j]);
+        for (int j = 0; j < 4; ++j) {
+            re[mt][j] = sum16_64(re[mt][j]);
+            im[mt][j] = sum16_64(im[mt][j]);
+        }
 }
 
 // One launch: blocks [0, H) take the boxes with more than M2L_HEAVY weak pairs
@@ -551,53 +627,73 @@ template <int MT, int KS, bool LOG>
 __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
 {
     __shared__ double part[M2L_WAVES][MT * 16][2];
+    // S_{l,k} = C(l + k, l) for rows l < 16 MT, k < 4 KS (zero beyond p, and
+    // for k = p: the highest coefficient a_{k+1} does not exist)
+    // followed by 1/l for the rows (the a_0 term of the log kernel)
+    __shared__ double Sop[MT * 16 * 4 * KS + MT * 16];
+    for (int t = threadIdx.x; t < MT * 16 * 4 * KS; t += blockDim.x) {
+        const int row = t / (4 * KS), kk = t % (4 * KS);
+        Sop[t] = (row <= a.p && kk < a.p) ? a.binom[(row + kk) * FMM_BN + row] : 0.0;
+    }
+    for (int t = threadIdx.x; t < MT * 16; t += blockDim.x) Sop[MT * 16 * 4 * KS + t] = t ? 1.0 / t : 0.0;
+    __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
-    const int col = lane & 15, ps = col >> 1, comp = col & 1, kq = lane >> 4;
+    const int pr = lane & 15, kq = lane >> 4;
     const int P1 = a.p + 1;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if ((int32_t)blockIdx.x >= H) {
-        const int64_t g = (int64_t)(blockIdx.x - H) * M2L_WAVES + w;
-        if (g >= a.nb) return;
-        int l;
+    const bool light = (int32_t)blockIdx.x >= H;
+    const int32_t nseg = light ? 0 : a.hoff[a.nb];
+    // light blocks: one box per wave, one pass; heavy blocks: segments of the
+    // heavy boxes (partial sums to hpart), blockIdx.x, + H, ...
+    for (int32_t sg = blockIdx.x;; sg += H) {
+        int64_t g;
+        int l, ww = 0, nw = 1;
         int32_t e0, e1;
-        if (m2l_range(a, g, l, e0, e1) > M2L_HEAVY) return;
-        double acc[MT][4];
-        m2l64_acc<MT, KS, LOG>(a, g, l, e0, e1, 0, 1, acc);
-        double2 *Bt = a.B + g * P1;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = 16 * mt + 4 * j + kq;
-                if (ps == 0 && row <= a.p) reinterpret_cast<double *>(Bt + row)[comp] = acc[mt][j];
-            }
-    } else {
-        // segments of the heavy boxes; partial sums go to hpart
-        const int32_t nseg = a.hoff[a.nb];
-        for (int32_t sg = blockIdx.x; sg < nseg; sg += H) {
-            const int64_t g = a.hbox[sg];
-            int l;
-            int32_t e0, e1;
+        if (light) {
+            g = (int64_t)(blockIdx.x - H) * M2L_WAVES + w;
+            if (g >= a.nb) return;
+            if (m2l_range(a, g, l, e0, e1) > M2L_HEAVY) return;
+        } else {
+            if (sg >= nseg) return; // uniform over the block
+            g = a.hbox[sg];
             m2l_range(a, g, l, e0, e1);
-            const int32_t s0 = min(e0 + (sg - a.hoff[g]) * M2L_SEG, e1), s1 = min(s0 + M2L_SEG, e1);
-            double acc[MT][4];
-            m2l64_acc<MT, KS, LOG>(a, g, l, s0, s1, w, M2L_WAVES, acc);
+            const int32_t s0 = min(e0 + (sg - a.hoff[g]) * M2L_SEG, e1);
+            e1 = min(s0 + M2L_SEG, e1);
+            e0 = s0;
+            ww = w;
+            nw = M2L_WAVES;
+        }
+        double re[MT][4], im[MT][4];
+        m2l64_acc<MT, KS, LOG>(a, Sop, g, l, e0, e1, ww, nw, re, im);
+        if (light) {
+            double2 *Bt = a.B + g * P1;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (ps == 0) part[w][16 * mt + 4 * j + kq][comp] = acc[mt][j];
-            __syncthreads();
-            if (w == 0) {
-                double2 *Bt = a.hpart + (int64_t)sg * P1;
-                for (int k = lane; k < 2 * P1; k += WAVE) {
-                    double v = 0.0;
-                    for (int q = 0; q < M2L_WAVES; ++q) v += part[q][k >> 1][k & 1];
-                    reinterpret_cast<double *>(Bt)[k] = v;
+                for (int j = 0; j < 4; ++j) {
+                    const int row = 16 * mt + 4 * j + kq;
+                    if (pr == 0 && row <= a.p) Bt[row] = make_double2(re[mt][j], im[mt][j]);
                 }
-            }
-            __syncthreads();
+            return;
         }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (pr == 0) {
+                    part[w][16 * mt + 4 * j + kq][0] = re[mt][j];
+                    part[w][16 * mt + 4 * j + kq][1] = im[mt][j];
+                }
+        __syncthreads();
+        if (w == 0) {
+            double2 *Bt = a.hpart + (int64_t)sg * P1;
+            for (int k = lane; k < 2 * P1; k += WAVE) {
+                double v = 0.0;
+                for (int q = 0; q < M2L_WAVES; ++q) v += part[q][k >> 1][k & 1];
+                reinterpret_cast<double *>(Bt)[k] = v;
+            }
+        }
+        __syncthreads();
     }
 }
 
