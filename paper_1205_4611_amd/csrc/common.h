@@ -15,6 +15,7 @@
 #define FMM_ST_LIST_OVERFLOW 1
 #define FMM_ST_ORDERS_SHORT 2   // caller's pair orders shorter than the weak list
 #define FMM_ST_TREE_INCONSISTENT 4 // internal check of the tree build failed
+#define FMM_LB_TILE 4096         // records per tile of the one-pass partition
 
 // learned truncation order
 #define FMM_NF FMM2D_PORDER_NFEAT
@@ -53,6 +54,10 @@ struct fmm_layout {
     size_t keys[2], vals[2];     // radix sort ping-pong (max(ns,nt) each)
     size_t hist;                 // radix histogram / scan block sums
     size_t srec, trec;           // 4 x n records (x- and y-ordered lists, ping-pong)
+    size_t srank;                // x and y presort orders, x and y rank of every source (4 ns)
+    size_t scoord;               // source x and y coordinates in sorted order (2 ns)
+    size_t lbst;                 // partition tile states (4 lists) and tickets
+    int64_t lbtiles;             // tiles per list
     size_t perm, tperm;          // leaf-order original indices (sources / targets)
     size_t bsum;                 // partition / scan block sums
     size_t sstep, tstep;         // per-step starts (sources / targets)

@@ -107,8 +107,12 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
         int64_t b = 4 * (fmm_scan_blocks(nmax) + 1);
         lay->bsum = take(4 * (a > b ? a : b));
     }
-    lay->srec = take(24 * 4 * ns);
+    lay->srec = take(12 * 4 * ns);
     lay->trec = take(24 * 4 * nt);
+    lay->srank = take(4 * 4 * ns);
+    lay->scoord = take(8 * 2 * ns);
+    lay->lbtiles = (nmax + FMM_LB_TILE - 1) / FMM_LB_TILE;
+    lay->lbst = take(8 * (4 * lay->lbtiles + 2));
     lay->perm = take(4 * ns);
     lay->tperm = take(4 * nt);
     lay->sstep = take(4 * lay->nstep);

@@ -288,30 +288,88 @@ static hipError_t radix_sort(int64_t n, int passes, uint64_t *k0, uint64_t *k1, 
     return hipMemcpyAsync(out, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
 }
 
-// Indices 0..n-1 of pts ordered by (coordinate `axis`, index).
+// Coordinate of each sorted key: the inverse of order_key, except that -0
+// and +0 share a key, so a zero key takes the point's own coordinate.
+__global__ void k_rs_decode(const uint64_t *__restrict__ keys, const int32_t *__restrict__ order,
+                            const double *__restrict__ pts, int64_t n, int axis, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint64_t k = keys[i];
+        double x;
+        if (k == 0x8000000000000000ull) {
+            x = pts[2 * min(max((int64_t)order[i], (int64_t)0), n - 1) + axis];
+        } else {
+            const uint64_t u = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+            x = __longlong_as_double((long long)u);
+        }
+        out[i] = x;
+    }
+}
+
+// Indices 0..n-1 of pts ordered by (coordinate `axis`, index) into out and,
+// if coord is not NULL, the coordinates in that order into coord.
 static hipError_t presort(const double *pts, int64_t n, int axis, uint64_t *k0, uint64_t *k1,
                           int32_t *v0, int32_t *v1, int32_t *hist, int32_t *bsum, int32_t *out,
-                          hipStream_t st)
+                          double *coord, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     k_rs_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pts, n, axis, k0, v0);
-    return radix_sort(n, 8, k0, k1, v0, v1, hist, bsum, out, st);
+    hipError_t e = radix_sort(n, 8, k0, k1, v0, v1, hist, bsum, out, st);
+    if (e != hipSuccess || !coord) return e;
+    // an even number of passes leaves the sorted keys in k0
+    k_rs_decode<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(k0, out, pts, n, axis, coord);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ splits --
 // Every point set is kept as two lists of self-describing records, one in
 // (x, index) order and one in (y, index) order inside every segment.  A record
-// carries its coordinates, original index and current segment, so the side of
-// a split follows from comparing the record with its segment's pivot: no
-// gathers through the original index, and stable partitions keep both lists
-// sorted inside every new segment.
+// carries its current segment, so the side of a split follows from comparing
+// the record with its segment's pivot: no gathers through the original index,
+// and stable partitions keep both lists sorted inside every new segment.
+//
+// Sources are records of ranks: rx, ry are the positions of the point in the
+// global (x, index) and (y, index) orders, so (x, index) < (x', index') is
+// exactly rx < rx'.  Coordinates are needed only at segment ends (rectangles)
+// and come from xs[rx], ys[ry], the coordinates in sorted order; the original
+// index is px[rx], px the x presort order.  Targets
+// (evaluation away from the sources) go below a pivot by coordinate alone and
+// keep their coordinates in the record.
+struct src_rec {
+    int32_t rx, ry, seg;
+};
 struct pt_rec {
     double x, y;
     int32_t idx, seg;
 };
 
-__global__ void k_rec_init(const double *__restrict__ pts, const int32_t *__restrict__ order, int64_t n,
-                           pt_rec *__restrict__ out)
+// Inverse permutations of the two presorts: rank of every original index.
+__global__ void k_rank_inv(const int32_t *__restrict__ px, const int32_t *__restrict__ py, int64_t n,
+                           int32_t *__restrict__ rxo, int32_t *__restrict__ ryo)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        rxo[min(max((int64_t)px[i], (int64_t)0), n - 1)] = (int32_t)i;
+        ryo[min(max((int64_t)py[i], (int64_t)0), n - 1)] = (int32_t)i;
+    }
+}
+
+__global__ void k_srec_init(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
+                            const int32_t *__restrict__ rxo, const int32_t *__restrict__ ryo, int64_t n,
+                            src_rec *__restrict__ lx, src_rec *__restrict__ ly)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int64_t vx = min(max((int64_t)px[i], (int64_t)0), n - 1);
+        const int64_t vy = min(max((int64_t)py[i], (int64_t)0), n - 1);
+        lx[i] = src_rec{(int32_t)i, ryo[vx], 0};
+        ly[i] = src_rec{rxo[vy], (int32_t)i, 0};
+    }
+}
+
+__global__ void k_trec_init(const double *__restrict__ pts, const int32_t *__restrict__ order, int64_t n,
+                            pt_rec *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -326,16 +384,19 @@ __global__ void k_rec_init(const double *__restrict__ pts, const int32_t *__rest
 }
 
 struct seg_args {
-    const pt_rec *slx, *sly;      // source lists
+    const src_rec *slx, *sly;     // source lists
+    const double *xs, *ys;        // source coordinates by rank
     const pt_rec *tlx, *tly;      // target lists (nt > 0)
     const int32_t *sst, *tst;     // step starts (nseg+1)
     int32_t *sst_next, *tst_next; // next step starts (2 nseg + 1), or NULL
     uint8_t *axis;
     double *pc;                   // pivot coordinate per segment
-    int32_t *pi;                  // pivot index per segment
+    int32_t *pi;                  // pivot rank (in the axis order) per segment
     int32_t *nlo, *tlo;
     double *centre, *radius;      // level arrays (already offset), or NULL
     int32_t *lvl_sst, *lvl_tst;   // per-level start output (already offset), or NULL
+    uint64_t *lb_clear;           // partition tile states to zero, or NULL
+    int64_t lb_n;
     int32_t nseg;
     int64_t ns, nt;
 };
@@ -343,9 +404,12 @@ struct seg_args {
 // One thread per segment: tight rectangle of its sources and targets, box
 // geometry (on even steps), split axis, pivot (the record at rank floor(n/2)
 // of the axis list) and the number of targets below the pivot coordinate.
+// The grid also zeroes the tile states of this step's partition.
 __global__ void k_seg(seg_args a)
 {
-    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = gt; i < a.lb_n; i += (int64_t)gridDim.x * blockDim.x) a.lb_clear[i] = 0;
+    const int32_t j = (int32_t)gt;
     if (j >= a.nseg) return;
     const int32_t s0 = a.sst[j], s1 = a.sst[j + 1];
     const int32_t n = s1 - s0;
@@ -353,10 +417,10 @@ __global__ void k_seg(seg_args a)
     const int32_t m = t1 - t0;
     double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
     if (n > 0) {
-        x0 = a.slx[s0].x;
-        x1 = a.slx[s1 - 1].x;
-        y0 = a.sly[s0].y;
-        y1 = a.sly[s1 - 1].y;
+        x0 = a.xs[a.slx[s0].rx];
+        x1 = a.xs[a.slx[s1 - 1].rx];
+        y0 = a.ys[a.sly[s0].ry];
+        y1 = a.ys[a.sly[s1 - 1].ry];
     }
     if (m > 0) {
         double u;
@@ -384,11 +448,11 @@ __global__ void k_seg(seg_args a)
     const int32_t nl = n / 2;
     int32_t tl = 0;
     double pcv = 0.0;
-    int32_t piv = 0;
+    int32_t prk = 0;
     if (n > 0) {
-        const pt_rec P = (ax ? a.sly : a.slx)[s0 + nl];
-        pcv = ax ? P.y : P.x;
-        piv = P.idx;
+        const src_rec P = (ax ? a.sly : a.slx)[s0 + nl];
+        prk = ax ? P.ry : P.rx;
+        pcv = ax ? a.ys[prk] : a.xs[prk];
     }
     if (n > 0 && m > 0) {
         const pt_rec *TA = ax ? a.tly : a.tlx;
@@ -402,7 +466,7 @@ __global__ void k_seg(seg_args a)
     }
     a.axis[j] = (uint8_t)ax;
     a.pc[j] = pcv;
-    a.pi[j] = piv;
+    a.pi[j] = prk;
     a.nlo[j] = nl;
     a.tlo[j] = tl;
     a.sst_next[2 * j] = s0;
@@ -415,109 +479,142 @@ __global__ void k_seg(seg_args a)
     }
 }
 
-struct part_list {
-    const pt_rec *in;
-    pt_rec *out;
-    int32_t *bsum;        // nblk + 1
+// Stable partition of every segment of a list by the side of each record, in
+// one pass (decoupled look-back).  Tiles of LB_B records are taken in the
+// order of a ticket counter; a tile publishes its lo count (AGG), sums the
+// counts of the tiles before it from their published states (stopping at the
+// first inclusive prefix, INC), publishes its own inclusive prefix and
+// scatters.  A tile only waits for tiles that took their ticket earlier and
+// are therefore running, and every wait is bounded.
+#define LB_T 256
+#define LB_I 16
+#define LB_B (LB_T * LB_I)
+static_assert(LB_B == FMM_LB_TILE, "partition tile size");
+#define LB_AGG 1ull
+#define LB_INC 2ull
+#define LB_SPIN (1 << 20)
+
+struct lb_list {
+    const void *in;
+    void *out;
+    uint64_t *state;      // ntiles words, zero before the launch
+    int32_t *ticket;      // zero before the launch
     const int32_t *start; // segment starts (nseg + 1)
     const int32_t *nlo;   // lo count per segment
     const int32_t *LO;    // exclusive scan of nlo
     int64_t n;
-    int32_t nseg;
-    int target;           // targets: lo iff coordinate < pivot coordinate
+    int32_t nseg, ntiles;
 };
-struct part_batch {
-    part_list l[4];
+struct lb_batch {
+    lb_list l[2];
     const uint8_t *axis;
     const double *pc;
     const int32_t *pi;
+    int32_t *status;
 };
 
-// Side of a record: sources go lo iff (coordinate, index) < pivot, targets
-// iff coordinate < pivot coordinate.
-__device__ __forceinline__ bool rec_lo(const part_batch &pb, const part_list &p, const pt_rec &r)
+// Side of a record: sources go lo iff their rank in the axis order is below
+// the pivot's, targets iff their coordinate is below the pivot coordinate.
+__device__ __forceinline__ bool rec_lo(const lb_batch &pb, int32_t j, const src_rec &r)
 {
-    const int32_t j = min(max(r.seg, 0), p.nseg - 1);
-    const double c = pb.axis[j] ? r.y : r.x;
-    const double pc = pb.pc[j];
-    if (p.target) return c < pc;
-    return c < pc || (c == pc && r.idx < pb.pi[j]);
+    return (pb.axis[j] ? r.ry : r.rx) < pb.pi[j];
+}
+__device__ __forceinline__ bool rec_lo(const lb_batch &pb, int32_t j, const pt_rec &r)
+{
+    return (pb.axis[j] ? r.y : r.x) < pb.pc[j];
 }
 
-// Records are read striped (record base + i*SCAN_T + thread) so that the
-// lanes of a wave touch consecutive records.
-__global__ void __launch_bounds__(SCAN_T) k_part_reduce(part_batch pb)
+template <typename R>
+__global__ void __launch_bounds__(LB_T) k_part_lb(lb_batch pb)
 {
-    const part_list &p = pb.l[blockIdx.y];
-    __shared__ int32_t sh[SCAN_T / WAVE];
-    if ((int64_t)blockIdx.x * SCAN_B >= p.n) return; // whole block idle (uniform)
-    const int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
-    int32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_I; ++i) {
-        const int64_t k = base + (int64_t)i * SCAN_T;
-        if (k < p.n) s += rec_lo(pb, p, p.in[k]);
-    }
-    int32_t tot;
-    block_excl_scan(s, sh, &tot);
-    if (threadIdx.x == 0) p.bsum[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(1024) k_part_sums(part_batch pb)
-{
-    const part_list &p = pb.l[blockIdx.x];
-    __shared__ int32_t sh[1024 / WAVE];
-    const int64_t nb = fmm_scan_blocks(p.n);
-    int32_t carry = 0;
-    for (int64_t c = 0; c < nb; c += blockDim.x) {
-        int64_t k = c + threadIdx.x;
-        int32_t v = k < nb ? p.bsum[k] : 0;
-        int32_t tot;
-        int32_t ex = block_excl_scan(v, sh, &tot);
-        if (k < nb) p.bsum[k] = carry + ex;
-        carry += tot;
-    }
-}
-
-__global__ void __launch_bounds__(SCAN_T) k_part_scatter(part_batch pb)
-{
-    const part_list &p = pb.l[blockIdx.y];
-    __shared__ int32_t wtot[SCAN_T / WAVE];
-    if ((int64_t)blockIdx.x * SCAN_B >= p.n) return;
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const lb_list &p = pb.l[blockIdx.y];
+    __shared__ int32_t s_tile, s_carry;
+    __shared__ int32_t wc[LB_I * (LB_T / WAVE)]; // lo count per (stripe, wave), then its exclusive scan
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    if (tid == 0) s_tile = atomicAdd(p.ticket, 1);
+    __syncthreads();
+    const int32_t tile = s_tile;
+    if (tile >= p.ntiles) return; // uniform over the block
+    const R *in = reinterpret_cast<const R *>(p.in);
+    R *out = reinterpret_cast<R *>(p.out);
+    const int64_t base = (int64_t)tile * LB_B + tid;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
-    const int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
-    int32_t carry = p.bsum[blockIdx.x]; // lo records before this block
+    R r[LB_I];
+    uint64_t mk[LB_I];
+    int32_t sg[LB_I];
 #pragma unroll
-    for (int i = 0; i < SCAN_I; ++i) {
-        const int64_t pos = base + (int64_t)i * SCAN_T;
-        const bool act = pos < p.n;
-        pt_rec r;
+    for (int i = 0; i < LB_I; ++i) {
+        const int64_t pos = base + (int64_t)i * LB_T;
         bool lo = false;
-        if (act) {
-            r = p.in[pos];
-            lo = rec_lo(pb, p, r);
+        sg[i] = -1;
+        if (pos < p.n) {
+            r[i] = in[pos];
+            sg[i] = min(max(r[i].seg, 0), p.nseg - 1);
+            lo = rec_lo(pb, sg[i], r[i]);
         }
-        const uint64_t m = __ballot(lo);
-        if (lane == 0) wtot[w] = __popcll(m);
-        __syncthreads();
-        int32_t before = carry + __popcll(m & lt), stripe = 0;
-        for (int q = 0; q < SCAN_T / WAVE; ++q) {
-            const int32_t t = wtot[q];
-            before += (q < w) ? t : 0;
-            stripe += t;
+        mk[i] = __ballot(lo);
+        if (lane == 0) wc[i * (LB_T / WAVE) + w] = __popcll(mk[i]);
+    }
+    __syncthreads();
+    if (w == 0) {
+        // exclusive scan of the 64 (stripe, wave) counts in stripe-major order
+        const int32_t v = wc[lane];
+        const int32_t inc = wave_incl_scan(v);
+        wc[lane] = inc - v;
+        const int32_t A = __shfl(inc, WAVE - 1, WAVE); // lo records of the tile
+        if (lane == 0)
+            __hip_atomic_store(p.state + tile, ((tile == 0 ? LB_INC : LB_AGG) << 32) | (uint32_t)A,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t prefix = 0;
+        if (tile > 0) {
+            int64_t t = tile - 1; // newest predecessor not yet summed
+            int spins = 0;
+            while (true) {
+                const int64_t tt = t - lane;
+                const uint64_t sv = tt >= 0 ? __hip_atomic_load(p.state + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                            : (LB_INC << 32);
+                const uint32_t fl = (uint32_t)(sv >> 32);
+                const uint64_t incm = __ballot(fl == LB_INC);
+                const uint64_t notready = __ballot(fl == 0);
+                const int k = incm ? (int)__builtin_ctzll(incm) : WAVE - 1; // lanes 0..k are summed
+                const uint64_t need = (k == WAVE - 1) ? ~0ull : ((2ull << k) - 1);
+                if (notready & need) {
+                    if (++spins > LB_SPIN) {
+                        if (lane == 0) atomicOr(pb.status, FMM_ST_TREE_INCONSISTENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                int32_t sum = (lane <= k) ? (int32_t)(uint32_t)sv : 0;
+#pragma unroll
+                for (int o = WAVE / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, WAVE);
+                prefix += sum;
+                if (incm) break;
+                t -= WAVE;
+            }
+            if (lane == 0)
+                __hip_atomic_store(p.state + tile, (LB_INC << 32) | (uint32_t)(prefix + A), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        __syncthreads();
-        carry += stripe;
-        if (act) {
-            const int32_t j = min(max(r.seg, 0), p.nseg - 1);
-            const int32_t st = p.start[j];
-            const int32_t rank = before - p.LO[j]; // lo records before pos in segment j
-            int64_t dst = lo ? (int64_t)st + rank : (int64_t)st + p.nlo[j] + (pos - st - rank);
-            dst = dst < 0 ? 0 : (dst >= p.n ? p.n - 1 : dst); // never leave the array
-            r.seg = 2 * j + (lo ? 0 : 1);
-            p.out[dst] = r;
-        }
+        if (lane == 0) s_carry = prefix;
+    }
+    __syncthreads();
+    const int32_t carry = s_carry;
+#pragma unroll
+    for (int i = 0; i < LB_I; ++i) {
+        if (sg[i] < 0) continue;
+        const int64_t pos = base + (int64_t)i * LB_T;
+        const int32_t j = sg[i];
+        const bool lo = (mk[i] >> lane) & 1;
+        const int32_t before = carry + wc[i * (LB_T / WAVE) + w] + __popcll(mk[i] & lt);
+        const int32_t st = p.start[j];
+        const int32_t rank = before - p.LO[j]; // lo records before pos in segment j
+        int64_t dst = lo ? (int64_t)st + rank : (int64_t)st + p.nlo[j] + (pos - st - rank);
+        dst = dst < 0 ? 0 : (dst >= p.n ? p.n - 1 : dst); // never leave the array
+        R o = r[i];
+        o.seg = 2 * j + (lo ? 0 : 1);
+        out[dst] = o;
     }
 }
 
@@ -525,19 +622,19 @@ __global__ void __launch_bounds__(SCAN_T) k_part_scatter(part_batch pb)
 // Evaluation at the sources: once every segment holds at most SUB_S sources,
 // one workgroup takes a segment through all its remaining splits in LDS and
 // writes the box geometry, the per-level starts and the leaf order itself.
-// Local point ids are positions in the segment's (x, index)-ordered list; the
-// segment's (y, index)-ordered list is read too and mapped to local ids with
-// an LDS hash table of the original indices.  The split rules are those of
-// the global steps (k_seg, rec_lo) in the same arithmetic, so the tree is the
-// same.
+// Local point ids are positions in the segment's x list; the segment's y list
+// is read too and mapped to local ids by binary search of its x ranks (the x
+// list is sorted by x rank).  Sides are decided on ranks and rectangles come
+// from the coordinates of the end points, as in the global steps, so the tree
+// is the same.
 #define SUB_S 2048
 #define SUB_T 512
 #define SUB_I (SUB_S / SUB_T)
-#define SUB_HBITS 12                       // hash table of 4096 slots
-#define SUB_UNI 22544                      // step tables, or the hash table
 
 struct subtree_args {
-    const pt_rec *lx, *ly;      // x and y lists after step k0
+    const src_rec *lx, *ly;     // x and y lists after step k0
+    const double *xs, *ys;      // coordinates by rank
+    const int32_t *px;          // original index by x rank
     const int32_t *sst;         // starts of the step-k0 segments (nseg0 + 1)
     int k0, L;
     int32_t nseg0;
@@ -548,65 +645,40 @@ struct subtree_args {
     int32_t *status;
 };
 
-__device__ __forceinline__ uint32_t sub_hash(int32_t idx)
-{
-    return ((uint32_t)idx * 2654435761u) >> (32 - SUB_HBITS);
-}
-
 __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
 {
-    __shared__ double px[SUB_S], py[SUB_S];
-    __shared__ int32_t pid[SUB_S];
-    __shared__ uint16_t lst[2][2][SUB_S]; // [buffer][x or y list][position] -> local id
-    __shared__ __align__(16) unsigned char uni[SUB_UNI];
+    __shared__ int32_t rxl[SUB_S], ryl[SUB_S], pid[SUB_S]; // by local id
+    __shared__ uint16_t lst[2][2][SUB_S];                   // [buffer][x or y list][position] -> local id
+    __shared__ uint16_t st[2][SUB_S + 1];                   // sub-segment starts
+    __shared__ uint16_t piv[SUB_S];                         // pivot local id per sub-segment
+    __shared__ uint8_t axs[SUB_S];                          // split axis per sub-segment
+    __shared__ uint16_t exs[2][SUB_S];                      // exclusive lo counts per position
     __shared__ int32_t sh[SUB_T / WAVE];
-    // step tables (after set-up) ...
-    uint16_t(*st)[SUB_S + 1] = reinterpret_cast<uint16_t(*)[SUB_S + 1]>(uni); // 8196 B
-    uint16_t *piv = reinterpret_cast<uint16_t *>(uni + 8200);                  // 4096 B
-    uint8_t *axs = uni + 12296;                                                // 2048 B
-    uint16_t(*exs)[SUB_S] = reinterpret_cast<uint16_t(*)[SUB_S]>(uni + 14344); // 8192 B
-    // ... or the hash table during set-up: local id per slot, -1 = empty
-    int32_t *hsh = reinterpret_cast<int32_t *>(uni);                           // 16384 B
     const int tid = threadIdx.x;
     const int32_t g0 = blockIdx.x;
     const int32_t base = a.sst[g0];
     const int32_t n = min(max(a.sst[g0 + 1] - base, 0), SUB_S);
-    for (int i = tid; i < (1 << SUB_HBITS); i += SUB_T) hsh[i] = -1;
     for (int i = tid; i < n; i += SUB_T) {
-        const pt_rec r = a.lx[base + i];
-        px[i] = r.x;
-        py[i] = r.y;
-        pid[i] = r.idx;
+        const src_rec r = a.lx[base + i];
+        rxl[i] = r.rx;
+        ryl[i] = r.ry;
+        pid[i] = a.px[min(max(r.rx, 0), (int32_t)a.ns - 1)];
         lst[0][0][i] = (uint16_t)i;
     }
     __syncthreads();
-    // local id of every original index (linear probing; at most n < 4096 occupied)
-    for (int i = tid; i < n; i += SUB_T) {
-        uint32_t h = sub_hash(pid[i]);
-        for (int probe = 0; probe < (1 << SUB_HBITS); ++probe) {
-            if (atomicCAS(&hsh[h], -1, i) == -1) break;
-            h = (h + 1) & ((1u << SUB_HBITS) - 1);
-        }
-    }
-    __syncthreads();
-    // the y list of the same points, as local ids (every index is present;
-    // the probe count is bounded all the same)
+    // the y list of the same points, as local ids
     bool missing = false;
     for (int i = tid; i < n; i += SUB_T) {
-        const int32_t idx = a.ly[base + i].idx;
-        uint32_t h = sub_hash(idx);
-        int32_t id = -1;
-        for (int probe = 0; probe < (1 << SUB_HBITS); ++probe) {
-            const int32_t c = hsh[h];
-            if (c < 0) break;
-            if (pid[c] == idx) { id = c; break; }
-            h = (h + 1) & ((1u << SUB_HBITS) - 1);
+        const int32_t rx = a.ly[base + i].rx;
+        int32_t lo_i = 0, hi_i = n - 1;
+        while (lo_i < hi_i) {
+            const int32_t mid = (lo_i + hi_i) >> 1;
+            if (rxl[mid] < rx) lo_i = mid + 1; else hi_i = mid;
         }
-        missing = missing || id < 0;
-        lst[0][1][i] = (uint16_t)(id < 0 ? 0 : id);
+        missing = missing || rxl[lo_i] != rx;
+        lst[0][1][i] = (uint16_t)lo_i;
     }
     if (missing) atomicOr(a.status, FMM_ST_TREE_INCONSISTENT);
-    __syncthreads();
     if (tid == 0) {
         st[0][0] = 0;
         st[0][1] = (uint16_t)n;
@@ -624,10 +696,10 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
             const int32_t s0 = st[cur][t], s1 = st[cur][t + 1], m = s1 - s0;
             double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
             if (m > 0) {
-                x0 = px[lst[cur][0][s0]];
-                x1 = px[lst[cur][0][s1 - 1]];
-                y0 = py[lst[cur][1][s0]];
-                y1 = py[lst[cur][1][s1 - 1]];
+                x0 = a.xs[rxl[lst[cur][0][s0]]];
+                x1 = a.xs[rxl[lst[cur][0][s1 - 1]]];
+                y0 = a.ys[ryl[lst[cur][1][s0]]];
+                y1 = a.ys[ryl[lst[cur][1][s1 - 1]]];
             }
             const double w = x1 - x0, h = y1 - y0;
             if (even) {
@@ -668,9 +740,7 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
                     }
                     t = lo_t;
                     const uint16_t id = lst[cur][q][p], pv = piv[t];
-                    const double c = axs[t] ? py[id] : px[id];
-                    const double pc = axs[t] ? py[pv] : px[pv];
-                    f = c < pc || (c == pc && pid[id] < pid[pv]);
+                    f = axs[t] ? (ryl[id] < ryl[pv]) : (rxl[id] < rxl[pv]);
                 }
                 lo[q][u] = f;
                 tseg[q][u] = t;
@@ -710,8 +780,8 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
         cur = nxt;
     }
     // (d) leaf order: inside every leaf the sources by ascending original
-    // index (px is free now: it holds the original index of each final position)
-    int32_t *pidl = reinterpret_cast<int32_t *>(px);
+    // index (rxl is free now: it holds the original index of each final position)
+    int32_t *pidl = rxl;
     for (int p = tid; p < n; p += SUB_T) pidl[p] = pid[lst[cur][0][p]];
     __syncthreads();
     const int32_t nleaf = 1 << J;
@@ -729,7 +799,8 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
     }
 }
 
-// Leaf of every original index (as the sort key) and the identity values.
+// Leaf of every original index (as the sort key) and the identity values;
+// a source's original index is px[rx].
 __global__ void k_leaf_keys(const pt_rec *__restrict__ lx, int64_t n, uint64_t *__restrict__ keys,
                             int32_t *__restrict__ vals)
 {
@@ -737,6 +808,17 @@ __global__ void k_leaf_keys(const pt_rec *__restrict__ lx, int64_t n, uint64_t *
     if (i < n) {
         const pt_rec r = lx[i];
         const int64_t v = min(max((int64_t)r.idx, (int64_t)0), n - 1);
+        keys[v] = (uint64_t)(uint32_t)r.seg;
+        vals[i] = (int32_t)i;
+    }
+}
+__global__ void k_leaf_keys_src(const src_rec *__restrict__ lx, const int32_t *__restrict__ px, int64_t n,
+                                uint64_t *__restrict__ keys, int32_t *__restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const src_rec r = lx[i];
+        const int64_t v = min(max((int64_t)px[min(max((int64_t)r.rx, (int64_t)0), n - 1)], (int64_t)0), n - 1);
         keys[v] = (uint64_t)(uint32_t)r.seg;
         vals[i] = (int32_t)i;
     }
@@ -915,11 +997,14 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     int32_t *bsum = WS(int32_t, lay.bsum);
     int32_t *perm = WS(int32_t, lay.perm), *tperm = nt ? WS(int32_t, lay.tperm) : nullptr;
     // record lists: [0] x-ordered, [1] y-ordered, [2], [3] partition outputs
-    pt_rec *sl[4], *tl[4];
+    src_rec *sl[4];
+    pt_rec *tl[4];
     for (int i = 0; i < 4; ++i) {
-        sl[i] = WS(pt_rec, lay.srec) + (int64_t)i * ns;
+        sl[i] = WS(src_rec, lay.srec) + (int64_t)i * ns;
         tl[i] = nt ? WS(pt_rec, lay.trec) + (int64_t)i * nt : nullptr;
     }
+    int32_t *px = WS(int32_t, lay.srank), *py = px + ns, *rxo = px + 2 * ns, *ryo = px + 3 * ns;
+    double *xs = WS(double, lay.scoord), *ys = xs + ns;
     int32_t *sstep = WS(int32_t, lay.sstep), *tstep = WS(int32_t, lay.tstep);
     uint8_t *axis = WS(uint8_t, lay.seg_axis);
     double *pc = WS(double, lay.seg_pc);
@@ -928,17 +1013,21 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     int32_t *LO = WS(int32_t, lay.seg_LO), *TLO = WS(int32_t, lay.seg_TLO);
     int32_t *sstart = WS(int32_t, lay.sstart), *tstart = WS(int32_t, lay.tstart);
     double *centre = WS(double, lay.centre), *radius = WS(double, lay.radius);
+    // partition tile states: 4 lists of lay.lbtiles words, then 4 tickets
+    uint64_t *lbst = WS(uint64_t, lay.lbst);
+    int32_t *ticket = reinterpret_cast<int32_t *>(lbst + 4 * lay.lbtiles);
+    const int64_t lb_n = 4 * lay.lbtiles + 2;
 
-    // presort into (coordinate, index) order, then records
-    CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, perm, st));
-    k_rec_init<<<nblk256(ns), 256, 0, st>>>(a.src, perm, ns, sl[0]);
-    CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, perm, st));
-    k_rec_init<<<nblk256(ns), 256, 0, st>>>(a.src, perm, ns, sl[1]);
+    // presort into (coordinate, index) order; source records of ranks
+    CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st));
+    CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, st));
+    k_rank_inv<<<nblk256(ns), 256, 0, st>>>(px, py, ns, rxo, ryo);
+    k_srec_init<<<nblk256(ns), 256, 0, st>>>(px, py, rxo, ryo, ns, sl[0], sl[1]);
     if (nt) {
-        CK(presort(a.tgt, nt, 0, k0s, k1, v0, v1, hist, bsum, tperm, st));
-        k_rec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[0]);
-        CK(presort(a.tgt, nt, 1, k0s, k1, v0, v1, hist, bsum, tperm, st));
-        k_rec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[1]);
+        CK(presort(a.tgt, nt, 0, k0s, k1, v0, v1, hist, bsum, tperm, nullptr, st));
+        k_trec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[0]);
+        CK(presort(a.tgt, nt, 1, k0s, k1, v0, v1, hist, bsum, tperm, nullptr, st));
+        k_trec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[1]);
     }
     k_root<<<1, 1, 0, st>>>(sstep, (int32_t)ns, tstep, (int32_t)nt);
     // At the sources, the steps from k0 on run in LDS (k_subtree): k0 is the
@@ -950,6 +1039,7 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
                 k0 = k;
                 break;
             }
+    const int32_t st_tiles = (int32_t)((ns + LB_B - 1) / LB_B), tt_tiles = (int32_t)((nt + LB_B - 1) / LB_B);
     int64_t soff_k = 0; // offset of step k's starts
     for (int k = 0; k <= 2 * L; ++k) {
         const int32_t nseg = (int32_t)(((int64_t)1) << k);
@@ -957,6 +1047,9 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
             subtree_args ta;
             ta.lx = sl[0];
             ta.ly = sl[1];
+            ta.xs = xs;
+            ta.ys = ys;
+            ta.px = px;
             ta.status = a.status;
             ta.sst = sstep + soff_k;
             ta.k0 = k0;
@@ -976,6 +1069,7 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         const int l = k / 2;
         seg_args sa;
         sa.slx = sl[0]; sa.sly = sl[1];
+        sa.xs = xs; sa.ys = ys;
         sa.tlx = tl[0]; sa.tly = tl[1];
         sa.sst = sstep + soff_k; sa.tst = tstep + soff_k;
         sa.sst_next = split ? sstep + soff_k + nseg + 1 : nullptr;
@@ -985,6 +1079,8 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         sa.radius = even ? radius + box_off(l) : nullptr;
         sa.lvl_sst = even ? sstart + start_off(l) : nullptr;
         sa.lvl_tst = even ? tstart + start_off(l) : nullptr;
+        sa.lb_clear = split ? lbst : nullptr;
+        sa.lb_n = split ? lb_n : 0;
         sa.nseg = nseg; sa.ns = ns; sa.nt = nt;
         k_seg<<<nblk256(nseg), 256, 0, st>>>(sa);
         CK(hipGetLastError());
@@ -992,37 +1088,33 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         // exclusive scans of the lo counts over segments
         CK(fmm_scan_i32(nlo, LO, nseg, nullptr, hist, st));
         if (nt) CK(fmm_scan_i32(tlo, TLO, nseg, nullptr, hist, st));
-        part_batch pb;
-        pb.axis = axis; pb.pc = pc; pb.pi = pi;
-        int nl = 0;
-        const int64_t bsum_stride = fmm_scan_blocks(ns > nt ? ns : nt) + 1;
+        lb_batch pb;
+        pb.axis = axis; pb.pc = pc; pb.pi = pi; pb.status = a.status;
         for (int q = 0; q < 2; ++q) {
-            part_list &p = pb.l[nl];
+            lb_list &p = pb.l[q];
             p.in = sl[q]; p.out = sl[2 + q];
-            p.bsum = bsum + (int64_t)nl * bsum_stride;
+            p.state = lbst + (int64_t)q * lay.lbtiles;
+            p.ticket = ticket + q;
             p.start = sstep + soff_k; p.nlo = nlo; p.LO = LO;
-            p.n = ns; p.nseg = nseg; p.target = 0;
-            ++nl;
+            p.n = ns; p.nseg = nseg; p.ntiles = st_tiles;
         }
+        k_part_lb<src_rec><<<dim3((unsigned)st_tiles, 2), LB_T, 0, st>>>(pb);
+        CK(hipGetLastError());
         if (nt) {
             for (int q = 0; q < 2; ++q) {
-                part_list &p = pb.l[nl];
+                lb_list &p = pb.l[q];
                 p.in = tl[q]; p.out = tl[2 + q];
-                p.bsum = bsum + (int64_t)nl * bsum_stride;
+                p.state = lbst + (int64_t)(2 + q) * lay.lbtiles;
+                p.ticket = ticket + 2 + q;
                 p.start = tstep + soff_k; p.nlo = tlo; p.LO = TLO;
-                p.n = nt; p.nseg = nseg; p.target = 1;
-                ++nl;
+                p.n = nt; p.nseg = nseg; p.ntiles = tt_tiles;
             }
+            k_part_lb<pt_rec><<<dim3((unsigned)tt_tiles, 2), LB_T, 0, st>>>(pb);
+            CK(hipGetLastError());
         }
-        const int64_t nmax = ns > nt ? ns : nt;
-        dim3 g((unsigned)fmm_scan_blocks(nmax), (unsigned)nl);
-        k_part_reduce<<<g, SCAN_T, 0, st>>>(pb);
-        k_part_sums<<<nl, 1024, 0, st>>>(pb);
-        k_part_scatter<<<g, SCAN_T, 0, st>>>(pb);
-        CK(hipGetLastError());
         for (int q = 0; q < 2; ++q) {
-            pt_rec *t = sl[q]; sl[q] = sl[2 + q]; sl[2 + q] = t;
-            if (nt) { t = tl[q]; tl[q] = tl[2 + q]; tl[2 + q] = t; }
+            src_rec *t = sl[q]; sl[q] = sl[2 + q]; sl[2 + q] = t;
+            if (nt) { pt_rec *u = tl[q]; tl[q] = tl[2 + q]; tl[2 + q] = u; }
         }
         soff_k += nseg + 1;
     }
@@ -1030,7 +1122,7 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     // sort of the identity by leaf number
     const int passes = (2 * L + 7) / 8;
     if (k0 < 0) {
-        k_leaf_keys<<<nblk256(ns), 256, 0, st>>>(sl[0], ns, k0s, v0);
+        k_leaf_keys_src<<<nblk256(ns), 256, 0, st>>>(sl[0], px, ns, k0s, v0);
         if (passes > 0) CK(radix_sort(ns, passes, k0s, k1, v0, v1, hist, bsum, perm, st));
         else CK(hipMemcpyAsync(perm, v0, (size_t)ns * 4, hipMemcpyDeviceToDevice, st));
     }
