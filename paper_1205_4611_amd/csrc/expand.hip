@@ -125,9 +125,39 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Lane layout of the leaf kernels (P2M, P2L): lane = 16 g + r, r a source
+// slot, g a group of P2_KG consecutive expansion terms k = P2_KG g + t.  A lane
+// takes the sources r, r + 16, ... and the terms of its group, so the sum over
+// sources is a reduction over the 16 lanes of a DPP row.
+template <int PM>
+struct p2_groups {
+    static constexpr int KG = (PM + 4) / 4; // 4 groups cover k = 0..PM
+};
+
+// z^E for a compile-time E by squaring
+template <int E>
+__device__ __forceinline__ double2 cpow_ct(double2 z)
+{
+    if constexpr (E == 0) {
+        return make_double2(1.0, 0.0);
+    } else if constexpr (E == 1) {
+        return z;
+    } else if constexpr ((E & 1) == 0) {
+        const double2 h = cpow_ct<E / 2>(z);
+        return cmul(h, h);
+    } else {
+        return cmul(z, cpow_ct<E - 1>(z));
+    }
+}
+// zK^g for the lane's group g in 0..3
+__device__ __forceinline__ double2 group_power(double2 zK, int g)
+{
+    const double2 z2 = cmul(zK, zK), z3 = cmul(z2, zK);
+    return g == 0 ? make_double2(1.0, 0.0) : (g == 1 ? zK : (g == 2 ? z2 : z3));
+}
+
 // ------------------------------------------------------------------ P2M --
-// One wave per leaf, one source per lane: every lane accumulates
-// s_k = sum m (x-c)^k in registers, then the wave reduces the 2(p+1) sums.
+// One wave per leaf: s_k = sum m (x-c)^k, then
 //   LOG:      a_0 = s_0, a_k = -s_k / k
 //   HARMONIC: a_0 = 0,   a_k = s_{k-1}
 template <int PM>
@@ -137,39 +167,38 @@ __global__ void __launch_bounds__(256) k_p2m(const double4 *__restrict__ srcs,
                                               double2 *__restrict__ A, int p, int kernel,
                                               int32_t nleaf)
 {
+    constexpr int KG = p2_groups<PM>::KG;
     const int lane = threadIdx.x & (WAVE - 1);
+    const int r = lane & 15, g = lane >> 4, kb = KG * g;
     const int32_t b = wave_index();
     if (b >= nleaf) return;
     const int32_t s0 = sst[b], s1 = sst[b + 1];
     const double cx = centre[2 * (int64_t)b], cy = centre[2 * (int64_t)b + 1];
-    double sr[PM + 1], si[PM + 1];
+    double sr[KG], si[KG];
 #pragma unroll
-    for (int k = 0; k <= PM; ++k) { sr[k] = 0.0; si[k] = 0.0; }
-    for (int32_t j = s0 + lane; j < s1; j += WAVE) {
+    for (int t = 0; t < KG; ++t) { sr[t] = 0.0; si[t] = 0.0; }
+    for (int32_t j = s0 + r; j < s1; j += 16) {
         const double4 d = srcs[j];
         const double2 w = make_double2(d.x - cx, d.y - cy);
-        double2 pw = make_double2(d.z, d.w);
+        double2 pw = cmul(make_double2(d.z, d.w), group_power(cpow_ct<KG>(w), g));
 #pragma unroll
-        for (int k = 0; k <= PM; ++k) {
-            if (k <= p) {
-                sr[k] += pw.x;
-                si[k] += pw.y;
-                pw = cmul(pw, w);
-            }
+        for (int t = 0; t < KG; ++t) {
+            sr[t] += pw.x;
+            si[t] += pw.y;
+            if (t + 1 < KG) pw = cmul(pw, w);
         }
     }
     double2 *out = A + (int64_t)b * (p + 1);
 #pragma unroll
-    for (int k = 0; k <= PM; ++k) {
-        if (k <= p) {
-            const double r = wave_sum(sr[k]), i = wave_sum(si[k]);
-            if (lane == 0) {
-                if (kernel == FMM2D_KERNEL_LOG) {
-                    out[k] = (k == 0) ? make_double2(r, i) : make_double2(-r / k, -i / k);
-                } else {
-                    if (k < p) out[k + 1] = make_double2(r, i);
-                    if (k == 0) out[0] = make_double2(0.0, 0.0);
-                }
+    for (int t = 0; t < KG; ++t) {
+        const double re = sum16_64(sr[t]), im = sum16_64(si[t]);
+        const int k = kb + t;
+        if (r == 0 && k <= p) {
+            if (kernel == FMM2D_KERNEL_LOG) {
+                out[k] = (k == 0) ? make_double2(re, im) : make_double2(-re / k, -im / k);
+            } else {
+                if (k < p) out[k + 1] = make_double2(re, im);
+                if (k == 0) out[0] = make_double2(0.0, 0.0);
             }
         }
     }
@@ -179,71 +208,90 @@ __global__ void __launch_bounds__(256) k_p2m(const double4 *__restrict__ srcs,
 // Leaf-level swapped criterion: sources of a larger box, outside the target
 // leaf's disc, go straight into its local expansion (added after L2L).  With
 // d = x - c and u = 1/d:
-//   LOG:      b_0 += m Log(c - x),   b_l -= m u^l / l      (l >= 1)
-//   HARMONIC: b_l -= m u^{l+1}                            (l >= 0)
-// One wave per leaf, one source per lane, wave reduction of the p+1 sums.
-template <int PM>
+//   LOG:      b_0 += sum m Log(c - x),   b_l -= (sum m u^l) / l   (l >= 1)
+//   HARMONIC: b_l -= sum m u^{l+1}                               (l >= 0)
+// One wave per target leaf; the list entries are read once, up to 64 at a
+// time.  The Log term of the log kernel is summed by all 64 lanes apart.
+template <int PM, bool LOG>
 __global__ void __launch_bounds__(256) k_p2l(const double4 *__restrict__ srcs,
                                               const int32_t *__restrict__ sst,
                                               const int32_t *__restrict__ poff,
                                               const int32_t *__restrict__ pidx,
                                               const double *__restrict__ centre,
-                                              double2 *__restrict__ B, int p, int kernel,
-                                              int32_t nleaf, int32_t lcap)
+                                              double2 *__restrict__ B, int p, int32_t nleaf, int32_t lcap)
 {
+    constexpr int KG = p2_groups<PM>::KG;
     const int lane = threadIdx.x & (WAVE - 1);
+    const int r = lane & 15, g = lane >> 4, kb = KG * g;
     const int32_t t = wave_index();
     if (t >= nleaf) return;
     const int32_t e0 = min(poff[t], lcap), e1 = min(poff[t + 1], lcap);
     if (e0 >= e1) return;
     const double cx = centre[2 * (int64_t)t], cy = centre[2 * (int64_t)t + 1];
-    const bool LOG = kernel == FMM2D_KERNEL_LOG;
-    double sr[PM + 1], si[PM + 1];
+    // LOG: the lane's terms start at u^kb; HARMONIC: at u^(kb+1)
+    double sr[KG], si[KG];
 #pragma unroll
-    for (int k = 0; k <= PM; ++k) { sr[k] = 0.0; si[k] = 0.0; }
-    for (int32_t e = e0; e < e1; ++e) {
-        const int32_t s = __builtin_amdgcn_readfirstlane(min(max(pidx[e], 0), nleaf - 1));
-        const int32_t j0 = sst[s], j1 = sst[s + 1];
-        for (int32_t j = j0 + lane; j < j1; j += WAVE) {
-            const double4 q = srcs[j];
-            const double2 u = cinv(make_double2(q.x - cx, q.y - cy));
-            double2 pw = make_double2(q.z, q.w);
-            if (LOG) {
-                const double lx = cx - q.x, ly = cy - q.y; // Log(c - x), formed as written
-                const double2 lg = make_double2(0.5 * log(lx * lx + ly * ly), atan2(ly, lx));
-                const double2 t0 = cmul(pw, lg);
-                sr[0] += t0.x;
-                si[0] += t0.y;
+    for (int q = 0; q < KG; ++q) { sr[q] = 0.0; si[q] = 0.0; }
+    double2 lg0 = make_double2(0.0, 0.0);
+    for (int32_t ec = e0; ec < e1; ec += WAVE) {
+        // this batch's source leaves and their ranges
+        int32_t mj0 = 0, mj1 = 0;
+        if (ec + lane < e1) {
+            const int32_t s = min(max(pidx[ec + lane], 0), nleaf - 1);
+            mj0 = sst[s];
+            mj1 = sst[s + 1];
+        }
+        const int32_t ne = min(e1 - ec, WAVE);
+        for (int32_t q = 0; q < ne; ++q) {
+            const int32_t j0 = __builtin_amdgcn_readlane(mj0, q), j1 = __builtin_amdgcn_readlane(mj1, q);
+            for (int32_t j = j0 + r; j < j1; j += 16) {
+                const double4 d = srcs[j];
+                const double2 u = cinv(make_double2(d.x - cx, d.y - cy));
+                double2 pw = cmul(make_double2(d.z, d.w), group_power(cpow_ct<KG>(u), g));
+                if (!LOG) pw = cmul(pw, u);
+#pragma unroll
+                for (int k = 0; k < KG; ++k) {
+                    sr[k] += pw.x;
+                    si[k] += pw.y;
+                    if (k + 1 < KG) pw = cmul(pw, u);
+                }
             }
-#pragma unroll
-            for (int k = 0; k <= PM; ++k) {
-                if (k <= p) {
-                    if (LOG) {
-                        if (k >= 1) {
-                            pw = cmul(pw, u);
-                            sr[k] -= pw.x / k;
-                            si[k] -= pw.y / k;
-                        }
-                    } else {
-                        pw = cmul(pw, u);
-                        sr[k] -= pw.x;
-                        si[k] -= pw.y;
-                    }
+            if (LOG) {
+                for (int32_t j = j0 + lane; j < j1; j += WAVE) {
+                    const double4 d = srcs[j];
+                    const double lx = cx - d.x, ly = cy - d.y; // Log(c - x), formed as written
+                    const double2 lg = make_double2(0.5 * log(lx * lx + ly * ly), atan2(ly, lx));
+                    const double2 t0 = cmul(make_double2(d.z, d.w), lg);
+                    lg0.x += t0.x;
+                    lg0.y += t0.y;
                 }
             }
         }
     }
     double2 *out = B + (int64_t)t * (p + 1);
+    if (LOG) {
+        lg0.x = wave_sum(lg0.x);
+        lg0.y = wave_sum(lg0.y);
+    }
 #pragma unroll
-    for (int k = 0; k <= PM; ++k) {
-        if (k <= p) {
-            const double r = wave_sum(sr[k]), i = wave_sum(si[k]);
-            if (lane == 0) {
-                double2 o = out[k];
-                o.x += r;
-                o.y += i;
-                out[k] = o;
+    for (int q = 0; q < KG; ++q) {
+        const double re = sum16_64(sr[q]), im = sum16_64(si[q]);
+        const int k = kb + q;
+        if (r == 0 && k <= p) {
+            double2 o = out[k];
+            if (LOG) {
+                if (k == 0) {
+                    o.x += lg0.x;
+                    o.y += lg0.y;
+                } else {
+                    o.x -= re / k;
+                    o.y -= im / k;
+                }
+            } else {
+                o.x -= re;
+                o.y -= im;
             }
+            out[k] = o;
         }
     }
 }
@@ -996,11 +1044,11 @@ static void launch_p2l(const fmm_eval_args &a, hipStream_t st)
     const fmm_layout &lay = *a.lay;
     const int64_t nleaf = nbox(a.L);
     const unsigned nblk = (unsigned)((nleaf + 3) / 4);
-    k_p2l<PM><<<nblk, 256, 0, st>>>(WSC(double4, lay.srcs), WSC(int32_t, lay.sstart) + start_off(a.L),
-                                    WSC(int32_t, lay.poff), WSC(int32_t, lay.pidx),
-                                    WSC(double, lay.centre) + 2 * box_off(a.L),
-                                    WSC(double2, lay.B) + box_off(a.L) * (a.p + 1), a.p, a.kernel,
-                                    (int32_t)nleaf, (int32_t)lay.leafcap);
+    auto k = a.kernel == FMM2D_KERNEL_LOG ? k_p2l<PM, true> : k_p2l<PM, false>;
+    k<<<nblk, 256, 0, st>>>(WSC(double4, lay.srcs), WSC(int32_t, lay.sstart) + start_off(a.L), WSC(int32_t, lay.poff),
+                            WSC(int32_t, lay.pidx), WSC(double, lay.centre) + 2 * box_off(a.L),
+                            WSC(double2, lay.B) + box_off(a.L) * (a.p + 1), a.p, (int32_t)nleaf,
+                            (int32_t)lay.leafcap);
 }
 
 hipError_t fmm_p2l(const fmm_eval_args &a, hipStream_t st)
