@@ -183,30 +183,12 @@ __global__ void __launch_bounds__(256) k_features(const double *__restrict__ cen
 // work is cut into the M2L work units (boxes of up to FMM_M2L_HEAVY weak pairs
 // and segments of FMM_M2L_SEG pairs of longer lists) so that very long lists
 // do not serialise:
-//   k_porder_units   one wave per unit: pair -> box map, share denominator
-//                    (partials of heavy boxes summed by k_porder_denred)
-//   k_porder_pairs   one thread per weak pair: features, MLP, order -> qw
-//   k_porder_sort    one wave per unit: the unit's pairs re-ordered by
-//                    increasing order (stable counting sort with ballots over
-//                    the unit's range of orders) into sw (source) and sp
-//                    (order), so that the M2L chunks of 8 pairs share similar
-//                    orders.
+//   k_porder         one wave per M2L work unit: features, MLP and order of
+//                    every pair of the unit, then the unit's pairs re-ordered
+//                    by increasing order (M2L chunks share similar orders).
 #define PORDER_RCH 8 // chunks of 64 pairs per sort unit (FMM_M2L_SEG / 64)
 static_assert(PORDER_RCH * 64 >= FMM_M2L_SEG && PORDER_RCH * 64 >= FMM_M2L_HEAVY,
               "a sort unit must fit the register window");
-
-__device__ __forceinline__ int wave_min_i(int v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
-    return v;
-}
-__device__ __forceinline__ int wave_max_i(int v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
-    return v;
-}
 
 __device__ __forceinline__ bool box_range(const int32_t *__restrict__ woff, int L, int64_t g, int32_t cap,
                                           int &l, int64_t &bo, int32_t &e0, int32_t &e1)
@@ -245,161 +227,122 @@ __device__ __forceinline__ bool porder_unit(const int32_t *__restrict__ woff, co
     return true;
 }
 
-// Per unit: the pair -> target box map, and the unit's part of the share
-// denominator (the whole sum for a light box, a segment partial otherwise).
-__global__ void __launch_bounds__(256) k_porder_units(const double *__restrict__ n1, const int32_t *__restrict__ woff,
-                                                      const int32_t *__restrict__ widx,
-                                                      const int32_t *__restrict__ hoff,
-                                                      const int32_t *__restrict__ hbox, int L, int64_t nb,
-                                                      int32_t cap, int32_t *__restrict__ pbox,
-                                                      double *__restrict__ den, double *__restrict__ dpart)
+// M2L body class of an order q: k-steps (q + 3) / 4 plus row tiles q / 16 + 1,
+// less one.  Both counts are non-decreasing in q, so equal classes mean equal
+// (row tiles, k-steps) and the class is non-decreasing in q; below 20 for q < 64.
+__device__ __forceinline__ int order_class(int q)
 {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t t = wave_index();
-    int64_t g, bo;
-    int l;
-    int32_t e0, e1;
-    if (!porder_unit(woff, hoff, hbox, L, nb, cap, t, g, l, bo, e0, e1)) {
-        if (t < nb && lane == 0) den[t] = 0.0; // heavy boxes are summed later; empty boxes 0
-        return;
-    }
-    const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
-    double s = 0.0;
-    for (int32_t e = e0 + lane; e < e1; e += WAVE) {
-        s += n1[bo + min(max(widx[e], 0), nbl - 1)];
-        pbox[e] = (int32_t)g;
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, WAVE);
-    if (lane == 0) {
-        if (t < nb) den[g] = s;
-        else dpart[t - nb] = s;
-    }
+    return ((q + 3) >> 2) + (q >> 4);
 }
 
-// Heavy boxes: the share denominator is the sum of the segment partials, in
-// segment order.
-__global__ void k_porder_denred(const int32_t *__restrict__ woff, const int32_t *__restrict__ hoff, int L,
-                                int64_t nb, int32_t cap, const double *__restrict__ dpart,
-                                double *__restrict__ den)
-{
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nb) return;
-    const int32_t n = hoff[g + 1] - hoff[g];
-    if (n == 0) return;
-    double s = 0.0;
-    for (int32_t k = 0; k < n; ++k) s += dpart[hoff[g] + k];
-    den[g] = s;
-}
-
-__global__ void __launch_bounds__(256) k_porder_pairs(const double *__restrict__ centre,
-                                                      const double *__restrict__ radius,
-                                                      const double *__restrict__ n1, const double *__restrict__ tail,
-                                                      const double *__restrict__ den,
-                                                      const int32_t *__restrict__ pbox,
-                                                      const int32_t *__restrict__ woff,
-                                                      const int32_t *__restrict__ widx,
-                                                      const float *__restrict__ model, float delta,
-                                                      const uint8_t *__restrict__ given, int64_t ngiven, int p,
-                                                      int L, int32_t cap, uint8_t *__restrict__ qw,
-                                                      int32_t *__restrict__ status)
+// One wave per M2L work unit (a box of at most FMM_M2L_HEAVY weak pairs, or
+// a segment of FMM_M2L_SEG pairs of a longer list; units t < nb are boxes,
+// t - nb indexes the segments).  The wave evaluates the order of each of the
+// unit's pairs (features and MLP, the caller's orders, or p), writes it in
+// weak-list order (qw) and re-orders the unit's pairs by increasing order
+// (stable counting sort with ballots over the unit's range of orders) into sw
+// (source) and sp (order), so that the pairs of an M2L chunk have similar
+// orders.  The target box's context, including the share denominator over its
+// whole weak list, is computed once per unit.
+__global__ void __launch_bounds__(256) k_porder(fmm_porder_args a, const float *__restrict__ model)
 {
     __shared__ float smodel[FMM2D_PORDER_MODEL_FLOATS];
+    // per wave: the unit's sources and orders (lane i keeps entries i, i + 64, ...)
+    __shared__ int32_t s_src[256 / WAVE][PORDER_RCH * WAVE];
+    __shared__ uint8_t s_q[256 / WAVE][PORDER_RCH * WAVE];
     if (model) {
         for (int k = threadIdx.x; k < FMM2D_PORDER_MODEL_FLOATS; k += blockDim.x) smodel[k] = model[k];
         __syncthreads();
     }
-    const float *mw = model ? smodel : nullptr;
-    const int64_t nst = d_start_off(L + 1);
-    const int32_t npairs = min(woff[nst - 1], cap);
-    bool short_given = false;
-    for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < npairs; e += gridDim.x * blockDim.x) {
-        int q = p;
-        if (mw) {
-            const int64_t g = pbox[e];
-            const int l = level_of_box(g, L);
-            const int64_t lo = d_start_off(l) + (g - d_box_off(l)); // entry of g in the offset arrays
-            const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
-            const int32_t s = widx[e];
-            feat_ctx c;
-            c.centre = centre; c.radius = radius; c.n1 = n1; c.tail = tail;
-            c.g = g; c.bo = d_box_off(l); c.l = l; c.L = L;
-            c.n1root = n1[0];
-            c.den = den[g];
-            c.nweak = woff[lo + 1] - woff[lo];
-            float f[FMM_NF];
-            pair_features(c, c.bo + min(max(s, 0), nbl - 1), f);
-            if (in_range(mw, f)) {
-                const float y = mlp_eval(mw, f) + delta;
-                const float yc = fminf(fmaxf(y, -1.0e6f), 1.0e6f); // NaN -> -1e6
-                const int qq = (int)ceilf(yc);
-                q = qq < FMM2D_PORDER_QMIN ? FMM2D_PORDER_QMIN : (qq > p ? p : qq);
-            }
-        } else if (given) {
-            if ((int64_t)e < ngiven) {
-                const int qq = given[e];
-                q = qq < 1 ? 1 : (qq > p ? p : qq);
-            } else {
-                short_given = true;
-            }
-        }
-        qw[e] = (uint8_t)q;
-    }
-    if (short_given) atomicOr(status, FMM_ST_ORDERS_SHORT);
-}
-
-// One wave per M2L work unit: a box of at most FMM_M2L_HEAVY weak pairs, or a
-// segment of FMM_M2L_SEG pairs of a longer list (units t < nb are boxes,
-// t - nb indexes the segments).  Within a unit the pairs are re-ordered by
-// increasing order; M2L only needs similar orders inside each chunk.
-__global__ void __launch_bounds__(256) k_porder_sort(const int32_t *__restrict__ woff,
-                                                     const int32_t *__restrict__ widx,
-                                                     const uint8_t *__restrict__ qw,
-                                                     const int32_t *__restrict__ hoff,
-                                                     const int32_t *__restrict__ hbox, int p, int L, int64_t nb,
-                                                     int32_t cap, int32_t *__restrict__ sw,
-                                                     uint8_t *__restrict__ sp)
-{
-    const int lane = threadIdx.x & (WAVE - 1);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const int64_t t = wave_index();
     int64_t g, bo;
     int l;
     int32_t e0, e1;
-    if (!porder_unit(woff, hoff, hbox, L, nb, cap, t, g, l, bo, e0, e1)) return;
-    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
-    const int32_t nent = e1 - e0; // <= FMM_M2L_SEG = PORDER_RCH * 64
-    int qr[PORDER_RCH];
-    int32_t sr[PORDER_RCH];
-    int qlo = p + 1, qhi = 0;
+    if (!porder_unit(a.woff, a.hoff, a.hbox, a.L, a.nb, a.cap, t, g, l, bo, e0, e1)) return;
+    const int32_t nbl = (int32_t)(((int64_t)1) << (2 * l));
+    int32_t *wsrc = s_src[wv];
+    uint8_t *wq = s_q[wv];
+    feat_ctx c;
+    if (a.model) {
+        // the whole box's list (a heavy box's segments each sum it, in one order)
+        int32_t E0, E1;
+        box_range(a.woff, a.L, g, a.cap, l, bo, E0, E1);
+        double den = 0.0;
+        for (int32_t e = E0 + lane; e < E1; e += WAVE) den += a.n1[bo + min(max(a.widx[e], 0), nbl - 1)];
 #pragma unroll
-    for (int k = 0; k < PORDER_RCH; ++k) {
+        for (int o = 32; o >= 1; o >>= 1) den += __shfl_xor(den, o, WAVE);
+        const int64_t so = d_start_off(l) + (g - bo);
+        c.centre = a.centre; c.radius = a.radius; c.n1 = a.n1; c.tail = a.tail;
+        c.g = g; c.bo = bo; c.l = l; c.L = a.L;
+        c.n1root = a.n1[0];
+        c.den = den;
+        c.nweak = a.woff[so + 1] - a.woff[so];
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+    const int32_t nent = min(e1 - e0, PORDER_RCH * WAVE); // <= FMM_M2L_SEG
+    const int32_t kmax = (nent + WAVE - 1) / WAVE;
+    bool short_given = false;
+#pragma unroll 1
+    for (int k = 0; k < kmax; ++k) {
         const int32_t i = k * WAVE + lane;
-        qr[k] = 0; // 0 never matches an order
-        sr[k] = 0;
+        wq[i] = 0; // 0 never matches an order
         if (i < nent) {
-            qr[k] = qw[e0 + i];
-            sr[k] = widx[e0 + i];
-            qlo = min(qlo, qr[k]);
-            qhi = max(qhi, qr[k]);
+            const int32_t e = e0 + i;
+            const int32_t s = a.widx[e];
+            int q = a.p;
+            if (a.model) {
+                float f[FMM_NF];
+                pair_features(c, bo + min(max(s, 0), nbl - 1), f);
+                // an opaque zero offset keeps the weights in LDS, read where
+                // they are used, instead of hoisted into registers
+                uint32_t off = 0;
+                asm volatile("" : "+v"(off));
+                const float *mw = smodel + off;
+                if (in_range(mw, f)) {
+                    const float y = mlp_eval(mw, f) + a.delta;
+                    const float yc = fminf(fmaxf(y, -1.0e6f), 1.0e6f); // NaN -> -1e6
+                    const int qq = (int)ceilf(yc);
+                    q = qq < FMM2D_PORDER_QMIN ? FMM2D_PORDER_QMIN : (qq > a.p ? a.p : qq);
+                }
+            } else if (a.given) {
+                if ((int64_t)e < a.ngiven) {
+                    const int qq = a.given[e];
+                    q = qq < 1 ? 1 : (qq > a.p ? a.p : qq);
+                } else {
+                    short_given = true;
+                }
+            }
+            a.qw[e] = (uint8_t)q;
+            wq[i] = (uint8_t)q;
+            wsrc[i] = s;
         }
     }
-    qlo = wave_min_i(qlo);
-    qhi = wave_max_i(qhi);
-    const int32_t kmax = (nent + WAVE - 1) / WAVE;
-    int32_t run = e0;
-    for (int qq = qlo; qq <= qhi; ++qq) {
+    if (short_given) atomicOr(a.status, FMM_ST_ORDERS_SHORT);
+    // stable sort by the M2L body class of the order (row tiles, k-steps):
+    // the classes present as a bit mask, then one pass per class
+    uint64_t present = 0;
+    for (int k = 0; k < kmax; ++k) {
+        const int32_t i = k * WAVE + lane;
+        if (i < nent) present |= 1ull << order_class(wq[i]);
+    }
 #pragma unroll
-        for (int k = 0; k < PORDER_RCH; ++k) {
-            if (k < kmax) {
-                const bool hit = qr[k] == qq;
-                const uint64_t m = __ballot(hit);
-                if (hit) {
-                    const int32_t dst = run + __popcll(m & lt);
-                    sw[dst] = sr[k];
-                    sp[dst] = (uint8_t)qq;
-                }
-                run += __popcll(m);
+    for (int o = 32; o >= 1; o >>= 1) present |= __shfl_xor(present, o, WAVE);
+    int32_t run = e0;
+    while (present) {
+        const int cls = __builtin_ctzll(present);
+        present &= present - 1;
+        for (int k = 0; k < kmax; ++k) {
+            const int32_t i = k * WAVE + lane;
+            const int q = wq[i];
+            const bool hit = i < nent && order_class(q) == cls;
+            const uint64_t m = __ballot(hit);
+            if (hit) {
+                const int32_t dst = run + __popcll(m & lt);
+                a.sw[dst] = wsrc[i];
+                a.sp[dst] = (uint8_t)q;
             }
+            run += __popcll(m);
         }
     }
 }
@@ -662,15 +605,7 @@ hipError_t fmm_features(const fmm_porder_args &a, int64_t nfeat_cap, float *feat
 hipError_t fmm_porder(const fmm_porder_args &a, hipStream_t st)
 {
     const unsigned nub = (unsigned)((a.nb + a.hmax + 3) / 4); // units: boxes, then heavy-box segments
-    if (a.model) {
-        k_porder_units<<<nub, 256, 0, st>>>(a.n1, a.woff, a.widx, a.hoff, a.hbox, a.L, a.nb, a.cap, a.pbox, a.den,
-                                            a.dpart);
-        k_porder_denred<<<(unsigned)((a.nb + 255) / 256), 256, 0, st>>>(a.woff, a.hoff, a.L, a.nb, a.cap, a.dpart,
-                                                                         a.den);
-    }
-    k_porder_pairs<<<2048, 256, 0, st>>>(a.centre, a.radius, a.n1, a.tail, a.den, a.pbox, a.woff, a.widx, a.model,
-                                         a.delta, a.given, a.ngiven, a.p, a.L, a.cap, a.qw, a.status);
-    k_porder_sort<<<nub, 256, 0, st>>>(a.woff, a.widx, a.qw, a.hoff, a.hbox, a.p, a.L, a.nb, a.cap, a.sw, a.sp);
+    k_porder<<<nub, 256, 0, st>>>(a, a.model);
     return hipGetLastError();
 }
 
