@@ -95,7 +95,7 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + (bytes ? bytes : 1)); return r; };
     const int64_t rs_blocks = (nmax + 4095) / 4096;
-    const int64_t hist_n = 256 * rs_blocks + 1;
+    const int64_t hist_n = 256 * rs_blocks + 256 * 8 + 1; // histograms and per-pass digit totals
     const int64_t seg_scan_n = fmm_scan_blocks(lay->nleaf + 1) + 1;
     lay->keys[0] = take(8 * nmax);
     lay->keys[1] = take(8 * nmax);

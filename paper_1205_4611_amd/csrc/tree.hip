@@ -152,6 +152,12 @@ hipError_t fmm_scan_i32(const int32_t *in, int32_t *out, int64_t n, const int32_
 // Stable LSD radix sort of (64-bit key, int32 value), 8-bit digits.  Starting
 // from the identity order, equal keys stay in index order, which is exactly
 // the (coordinate, index) order the split rule asks for.
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 #define RS_T 256
 #define RS_TILES 16
 #define RS_BLOCK (RS_T * RS_TILES)
@@ -173,6 +179,7 @@ __global__ void k_rs_init(const double *__restrict__ pts, int64_t n, int axis,
     }
 }
 
+// Per-block digit histogram of one pass: hist[digit][block].
 __global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t *__restrict__ keys, int64_t n,
                                                    int shift, int32_t *__restrict__ hist, int nblk)
 {
@@ -188,11 +195,56 @@ __global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t *__restrict__ k
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// Scatter of one pass.  The block's 4096 elements get their stable rank
-// within their digit (16 sub-tiles of 256 in order, peers of a digit found by
-// ballots over its 8 bits), are staged in LDS in digit order, and are then
+// Digit totals: block d sums column d of the histogram.
+__global__ void __launch_bounds__(1024) k_rs_coltot(const int32_t *__restrict__ hist, int nblk,
+                                                     int32_t *__restrict__ tot)
+{
+    __shared__ int32_t sh[1024 / WAVE];
+    const int32_t *col = hist + (int64_t)blockIdx.x * nblk;
+    int32_t v = 0;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) v += col[k];
+    int32_t t;
+    block_excl_scan(v, sh, &t);
+    if (threadIdx.x == 0) tot[blockIdx.x] = t;
+}
+
+// Scatter offsets of one pass: block d scans column d of the histogram and
+// adds the elements of all smaller digits: off[d][b] = sum_{d' < d} tot[d'] +
+// sum_{b' < b} hist[d][b'].
+__global__ void __launch_bounds__(1024) k_rs_offsets(const int32_t *__restrict__ hist, const int32_t *__restrict__ tot,
+                                                      int nblk, int32_t *__restrict__ off)
+{
+    __shared__ int32_t sh[1024 / WAVE];
+    __shared__ int32_t s_base;
+    const int d = blockIdx.x;
+    if (threadIdx.x < WAVE) {
+        int32_t v = 0;
+        for (int e = threadIdx.x; e < d; e += WAVE) v += tot[e];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+        if (threadIdx.x == 0) s_base = v;
+    }
+    __syncthreads();
+    int32_t carry = s_base;
+    const int32_t *col = hist + (int64_t)d * nblk;
+    int32_t *ocol = off + (int64_t)d * nblk;
+    for (int c0 = 0; c0 < nblk; c0 += blockDim.x) {
+        const int k = c0 + threadIdx.x;
+        const int32_t v = k < nblk ? col[k] : 0;
+        int32_t t;
+        const int32_t ex = block_excl_scan(v, sh, &t);
+        if (k < nblk) ocol[k] = carry + ex;
+        carry += t;
+    }
+}
+
+// Scatter of one pass.  Wave w of a block takes the block's elements
+// [w RS_BLOCK/4, (w+1) RS_BLOCK/4) 64 at a time and ranks each within its
+// digit with wave-private counters (peers of a digit found by ballots over its
+// 8 bits), so the loop has no block barrier; the four waves' counts then give
+// every element its place in the block's digit-ordered tile, staged in LDS and
 // written out so that consecutive threads write consecutive addresses of a
-// digit's run.
+// digit's run.  Stable: the block's order is wave-major, then in order.
 __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict__ kin,
                                                       const int32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout,
@@ -200,26 +252,31 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
                                                       int shift, const int32_t *__restrict__ off,
                                                       int nblk)
 {
+    constexpr int NW = RS_T / WAVE, PER_W = RS_BLOCK / NW, IT = PER_W / WAVE;
     __shared__ uint64_t sk[RS_BLOCK];
     __shared__ int32_t sv[RS_BLOCK];
-    __shared__ int32_t cnt[256];
+    __shared__ int32_t wc[NW][256]; // per-wave digit counts, then per-wave digit bases
     __shared__ int32_t dstart[256];
-    __shared__ int32_t wc[RS_T / WAVE][256];
-    __shared__ int32_t sh[RS_T / WAVE];
+    __shared__ int32_t sh[NW];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-    cnt[tid] = 0;
-    for (int q = 0; q < RS_T / WAVE; ++q) wc[q][tid] = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) wc[q][tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_BLOCK;
+    const int64_t wbase = base + (int64_t)w * PER_W;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
-    uint64_t key[RS_TILES];
-    int32_t val[RS_TILES], rk[RS_TILES];
+    uint64_t key[IT];
+    int32_t val[IT], rk[IT];
 #pragma unroll
-    for (int t = 0; t < RS_TILES; ++t) {
-        const int64_t k = base + (int64_t)t * RS_T + tid;
+    for (int t = 0; t < IT; ++t) {
+        const int64_t k = wbase + (int64_t)t * WAVE + lane;
         const bool valid = k < n;
         key[t] = valid ? kin[k] : 0ull;
         val[t] = valid ? vin[k] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        const bool valid = wbase + (int64_t)t * WAVE + lane < n;
         const int d = (int)((key[t] >> shift) & 255);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -228,29 +285,29 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
             const uint64_t bb = __ballot(bit);
             peers &= bit ? bb : ~bb;
         }
-        const int rank = __popcll(peers & lt);
-        if (valid && rank == 0) wc[w][d] = __popcll(peers);
-        __syncthreads();
-        int32_t r = cnt[d] + rank;
-        for (int q = 0; q < w; ++q) r += wc[q][d];
-        rk[t] = valid ? r : -1;
-        __syncthreads();
-        int32_t add = 0;
-        for (int q = 0; q < RS_T / WAVE; ++q) {
-            add += wc[q][tid];
-            wc[q][tid] = 0;
-        }
-        cnt[tid] += add;
-        __syncthreads();
+        const int32_t c = wc[w][d];
+        rk[t] = valid ? c + __popcll(peers & lt) : -1;
+        if (valid && __popcll(peers & lt) == 0) wc[w][d] = c + __popcll(peers);
     }
-    int32_t tot;
-    dstart[tid] = block_excl_scan(cnt[tid], sh, &tot);
+    __syncthreads();
+    {
+        // thread tid = digit: bases of the waves, the block's count, its start
+        int32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int32_t v = wc[q][tid];
+            wc[q][tid] = s;
+            s += v;
+        }
+        int32_t tot;
+        dstart[tid] = block_excl_scan(s, sh, &tot);
+    }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < RS_TILES; ++t) {
+    for (int t = 0; t < IT; ++t) {
         if (rk[t] >= 0) {
             const int d = (int)((key[t] >> shift) & 255);
-            const int p = min(dstart[d] + rk[t], RS_BLOCK - 1);
+            const int p = min(dstart[d] + wc[w][d] + rk[t], RS_BLOCK - 1);
             sk[p] = key[t];
             sv[p] = val[t];
         }
@@ -269,19 +326,22 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
 
 // LSD radix sort of (k0, v0) over `passes` 8-bit digits (ping-pong through
 // k1, v1); the values end up in out.  Stable, so equal keys keep their order.
+// hist holds 256 * nblk + 256 ints (histograms, scanned in place into the
+// scatter offsets, then the digit totals).
 static hipError_t radix_sort(int64_t n, int passes, uint64_t *k0, uint64_t *k1, int32_t *v0, int32_t *v1,
                              int32_t *hist, int32_t *bsum, int32_t *out, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     const int nblk = (int)((n + RS_BLOCK - 1) / RS_BLOCK);
+    int32_t *off = hist, *tot = hist + (int64_t)256 * nblk;
     uint64_t *ka = k0, *kb = k1;
     int32_t *va = v0, *vb = v1;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
         k_rs_hist<<<nblk, RS_T, 0, st>>>(ka, n, shift, hist, nblk);
-        hipError_t e = fmm_scan_i32(hist, hist, (int64_t)256 * nblk, nullptr, bsum, st);
-        if (e != hipSuccess) return e;
-        k_rs_scatter<<<nblk, RS_T, 0, st>>>(ka, va, kb, vb, n, shift, hist, nblk);
+        k_rs_coltot<<<256, 1024, 0, st>>>(hist, nblk, tot);
+        k_rs_offsets<<<256, 1024, 0, st>>>(hist, tot, nblk, off);
+        k_rs_scatter<<<nblk, RS_T, 0, st>>>(ka, va, kb, vb, n, shift, off, nblk);
         uint64_t *tk = ka; ka = kb; kb = tk;
         int32_t *tv = va; va = vb; vb = tv;
     }
@@ -945,11 +1005,6 @@ __global__ void __launch_bounds__(256) k_lists(list_args a)
     }
 }
 
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
 
 __global__ void k_root(int32_t *sstep, int32_t ns, int32_t *tstep, int32_t nt)
 {
