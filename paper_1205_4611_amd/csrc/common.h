@@ -29,6 +29,22 @@ static inline int64_t start_off(int l) { return box_off(l) + l; }
 // tells the compiler the value is wave-uniform, so everything derived from it
 // (loop bounds, list entries, source records) lives in scalar registers and is
 // fetched with scalar loads.
+// Position of block b among the blocks [b0, b1) of a launch, so that each
+// XCD takes runs of XCD_RUN consecutive positions: workgroups go to the 8 XCDs
+// round-robin (XCD = b mod 8), and a run of neighbouring leaves in one XCD
+// finds the data it shares in that XCD's L2; runs go to the XCDs in turn,
+// which spreads uneven work.  Blocks past the last whole group of 8 runs keep
+// their place.  A bijection onto [0, b1 - b0) whatever the hardware order.
+#define XCD_RUN 16
+__device__ __forceinline__ int32_t xcd_order(int32_t b, int32_t b0, int32_t b1)
+{
+    const int32_t r = b - b0, n = b1 - b0;
+    const int32_t full = n / (8 * XCD_RUN) * (8 * XCD_RUN);
+    if (r >= full) return r;
+    const int32_t x = r & 7, i = r >> 3; // XCD (relative to b0) and rank on it
+    return ((i / XCD_RUN) * 8 + x) * XCD_RUN + i % XCD_RUN;
+}
+
 __device__ __forceinline__ int32_t wave_index()
 {
     return __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64));

@@ -698,7 +698,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
         int l, ww = 0, nw = 1;
         int32_t e0, e1;
         if (light) {
-            g = (int64_t)(blockIdx.x - H) * M2L_WAVES + w;
+            g = (int64_t)xcd_order((int32_t)blockIdx.x, H, (int32_t)gridDim.x) * M2L_WAVES + w;
             if (g >= a.nb) return;
             if (m2l_range(a, g, l, e0, e1) > M2L_HEAVY) return;
         } else {
