@@ -703,6 +703,9 @@ struct subtree_args {
     int32_t *sstart;            // per-level starts, all levels
     int32_t *perm;
     int32_t *status;
+    const double *src, *m;      // caller's sources and strengths
+    double4 *srcs;              // sources with strengths in leaf order
+    float2 *m32;                // FP32 strengths in leaf order, or NULL
 };
 
 __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
@@ -855,7 +858,13 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
         const int32_t me = pidl[p];
         int32_t r = 0;
         for (int32_t k = s0; k < s1; ++k) r += pidl[k] < me;
-        a.perm[base + s0 + min(r, s1 - s0 - 1)] = me;
+        const int64_t pos = base + s0 + min(r, s1 - s0 - 1);
+        a.perm[pos] = me;
+        // the leaf-ordered sources (the gather of the global path)
+        const int64_t j = min(max((int64_t)me, (int64_t)0), a.ns - 1);
+        const double2 mm = reinterpret_cast<const double2 *>(a.m)[j];
+        a.srcs[pos] = make_double4(a.src[2 * j], a.src[2 * j + 1], mm.x, mm.y);
+        if (a.m32) a.m32[pos] = make_float2((float)mm.x, (float)mm.y);
     }
 }
 
@@ -1115,6 +1124,10 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
             ta.radius = radius;
             ta.sstart = sstart;
             ta.perm = perm;
+            ta.src = a.src;
+            ta.m = m;
+            ta.srcs = WS(double4, lay.srcs);
+            ta.m32 = lay.mixed == 1 ? WS(float2, lay.m32) : nullptr;
             k_subtree<<<(unsigned)nseg, SUB_T, 0, st>>>(ta);
             CK(hipGetLastError());
             break;
@@ -1186,7 +1199,7 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         if (passes > 0) CK(radix_sort(nt, passes, k0s, k1, v0, v1, hist, bsum, tperm, st));
         else CK(hipMemcpyAsync(tperm, v0, (size_t)nt * 4, hipMemcpyDeviceToDevice, st));
     }
-    {
+    if (k0 < 0) { // (the LDS subtree writes the leaf-ordered sources itself)
         int64_t nmax = ns > nt ? ns : nt;
         k_gather<<<nblk256(nmax), 256, 0, st>>>(a.src, m, perm, ns, WS(double4, lay.srcs),
                                                 lay.mixed == 1 ? WS(float2, lay.m32) : nullptr, a.tgt,
