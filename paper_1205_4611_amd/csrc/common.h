@@ -78,6 +78,10 @@ struct fmm_layout {
     size_t bsum;                 // partition / scan block sums
     size_t sstep, tstep;         // per-step starts (sources / targets)
     size_t seg_axis, seg_pc, seg_pi, seg_nlo, seg_tlo, seg_LO, seg_TLO;
+    size_t seg_nlox, seg_nloy, seg_LOy; // lo counts of the moving source lists, prefix of the y one
+    size_t sbits;                // per segment and source list: the buffer holding it (current, next)
+    size_t stseg;                // per source partition tile: the segment of its first position
+    size_t stcnt;                // per source list and tile: moving lo count, then its prefix
     size_t sstart, tstart;       // per-level starts (output)
     size_t centre, radius;
     size_t wcnt, scnt;           // per-box list counts (current level)

@@ -107,7 +107,10 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
         int64_t b = 4 * (fmm_scan_blocks(nmax) + 1);
         lay->bsum = take(4 * (a > b ? a : b));
     }
-    lay->srec = take(12 * 4 * ns);
+    lay->srec = take(8 * 4 * ns);
+    lay->sbits = take(4 * (lay->nleaf + 1));
+    lay->stseg = take(4 * ((ns + FMM_LB_TILE - 1) / FMM_LB_TILE + 1));
+    lay->stcnt = take(4 * 2 * ((ns + FMM_LB_TILE - 1) / FMM_LB_TILE + 1));
     lay->trec = take(24 * 4 * nt);
     lay->srank = take(4 * 4 * ns);
     lay->scoord = take(8 * 2 * ns);
@@ -124,6 +127,9 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->seg_tlo = take(4 * (lay->nleaf + 1));
     lay->seg_LO = take(4 * (lay->nleaf + 2));
     lay->seg_TLO = take(4 * (lay->nleaf + 2));
+    lay->seg_nlox = take(4 * (lay->nleaf + 1));
+    lay->seg_nloy = take(4 * (lay->nleaf + 1));
+    lay->seg_LOy = take(4 * (lay->nleaf + 2));
     lay->sstart = take(4 * lay->nstart);
     lay->tstart = take(4 * lay->nstart);
     lay->centre = take(16 * lay->nb);

@@ -152,6 +152,11 @@ hipError_t fmm_scan_i32(const int32_t *in, int32_t *out, int64_t n, const int32_
 // Stable LSD radix sort of (64-bit key, int32 value), 8-bit digits.  Starting
 // from the identity order, equal keys stay in index order, which is exactly
 // the (coordinate, index) order the split rule asks for.
+__global__ void k_fill_u8(uint8_t *p, int64_t n)
+{
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -393,11 +398,15 @@ static hipError_t presort(const double *pts, int64_t n, int axis, uint64_t *k0, 
 // global (x, index) and (y, index) orders, so (x, index) < (x', index') is
 // exactly rx < rx'.  Coordinates are needed only at segment ends (rectangles)
 // and come from xs[rx], ys[ry], the coordinates in sorted order; the original
-// index is px[rx], px the x presort order.  Targets
+// index is px[rx], px the x presort order.  A split along axis a leaves the
+// segment's a-ordered list as it is (its first floor(n/2) records are the lo
+// side), so only the other list moves: each list has two buffers and every
+// segment a bit per list saying which buffer holds its records; a record's
+// segment follows from its position.  Targets
 // (evaluation away from the sources) go below a pivot by coordinate alone and
 // keep their coordinates in the record.
 struct src_rec {
-    int32_t rx, ry, seg;
+    int32_t rx, ry;
 };
 struct pt_rec {
     double x, y;
@@ -423,8 +432,8 @@ __global__ void k_srec_init(const int32_t *__restrict__ px, const int32_t *__res
     if (i < n) {
         const int64_t vx = min(max((int64_t)px[i], (int64_t)0), n - 1);
         const int64_t vy = min(max((int64_t)py[i], (int64_t)0), n - 1);
-        lx[i] = src_rec{(int32_t)i, ryo[vx], 0};
-        ly[i] = src_rec{rxo[vy], (int32_t)i, 0};
+        lx[i] = src_rec{(int32_t)i, ryo[vx]};
+        ly[i] = src_rec{rxo[vy], (int32_t)i};
     }
 }
 
@@ -443,8 +452,18 @@ __global__ void k_trec_init(const double *__restrict__ pts, const int32_t *__res
     }
 }
 
+// partition tiles: LB_T threads, LB_I records each
+#define LB_T 256
+#define LB_I 16
+#define LB_B (LB_T * LB_I)
+static_assert(LB_B == FMM_LB_TILE, "partition tile size");
+
 struct seg_args {
-    const src_rec *slx, *sly;     // source lists
+    const src_rec *slx[2], *sly[2]; // source lists (two buffers each)
+    const uint8_t *bx, *by;       // per segment: the buffer holding its x / y list
+    uint8_t *bx_next, *by_next;   // the same for the next step's segments
+    int32_t *nlox, *nloy;         // lo counts of the lists that move (0 where a list stays)
+    int32_t *tseg;                // per partition tile: the segment holding its first position, or NULL
     const double *xs, *ys;        // source coordinates by rank
     const pt_rec *tlx, *tly;      // target lists (nt > 0)
     const int32_t *sst, *tst;     // step starts (nseg+1)
@@ -476,11 +495,13 @@ __global__ void k_seg(seg_args a)
     const int32_t t0 = a.nt ? a.tst[j] : 0, t1 = a.nt ? a.tst[j + 1] : 0;
     const int32_t m = t1 - t0;
     double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    const src_rec *LX = a.slx[a.bx[j] & 1], *LY = a.sly[a.by[j] & 1];
+    const int32_t rmax = (int32_t)a.ns - 1; // ranks index the sorted coordinates
     if (n > 0) {
-        x0 = a.xs[a.slx[s0].rx];
-        x1 = a.xs[a.slx[s1 - 1].rx];
-        y0 = a.ys[a.sly[s0].ry];
-        y1 = a.ys[a.sly[s1 - 1].ry];
+        x0 = a.xs[min(max(LX[s0].rx, 0), rmax)];
+        x1 = a.xs[min(max(LX[s1 - 1].rx, 0), rmax)];
+        y0 = a.ys[min(max(LY[s0].ry, 0), rmax)];
+        y1 = a.ys[min(max(LY[s1 - 1].ry, 0), rmax)];
     }
     if (m > 0) {
         double u;
@@ -510,9 +531,9 @@ __global__ void k_seg(seg_args a)
     double pcv = 0.0;
     int32_t prk = 0;
     if (n > 0) {
-        const src_rec P = (ax ? a.sly : a.slx)[s0 + nl];
+        const src_rec P = (ax ? LY : LX)[s0 + nl];
         prk = ax ? P.ry : P.rx;
-        pcv = ax ? a.ys[prk] : a.xs[prk];
+        pcv = ax ? a.ys[min(max(prk, 0), rmax)] : a.xs[min(max(prk, 0), rmax)];
     }
     if (n > 0 && m > 0) {
         const pt_rec *TA = ax ? a.tly : a.tlx;
@@ -529,6 +550,17 @@ __global__ void k_seg(seg_args a)
     a.pi[j] = prk;
     a.nlo[j] = nl;
     a.tlo[j] = tl;
+    // the list along the axis stays; the other moves to the other buffer
+    a.nlox[j] = ax ? nl : 0;
+    a.nloy[j] = ax ? 0 : nl;
+    if (a.tseg) // tiles whose first position lies in [s0, s1)
+        for (int64_t t = ((int64_t)s0 + LB_B - 1) / LB_B; t * LB_B < s1; ++t) a.tseg[t] = j;
+    const uint8_t nbx = ax ? (uint8_t)(1 - (a.bx[j] & 1)) : a.bx[j];
+    const uint8_t nby = ax ? a.by[j] : (uint8_t)(1 - (a.by[j] & 1));
+    a.bx_next[2 * j] = nbx;
+    a.bx_next[2 * j + 1] = nbx;
+    a.by_next[2 * j] = nby;
+    a.by_next[2 * j + 1] = nby;
     a.sst_next[2 * j] = s0;
     a.sst_next[2 * j + 1] = s0 + nl;
     if (j == a.nseg - 1) a.sst_next[2 * a.nseg] = s1;
@@ -546,10 +578,6 @@ __global__ void k_seg(seg_args a)
 // first inclusive prefix, INC), publishes its own inclusive prefix and
 // scatters.  A tile only waits for tiles that took their ticket earlier and
 // are therefore running, and every wait is bounded.
-#define LB_T 256
-#define LB_I 16
-#define LB_B (LB_T * LB_I)
-static_assert(LB_B == FMM_LB_TILE, "partition tile size");
 #define LB_AGG 1ull
 #define LB_INC 2ull
 #define LB_SPIN (1 << 20)
@@ -573,12 +601,7 @@ struct lb_batch {
     int32_t *status;
 };
 
-// Side of a record: sources go lo iff their rank in the axis order is below
-// the pivot's, targets iff their coordinate is below the pivot coordinate.
-__device__ __forceinline__ bool rec_lo(const lb_batch &pb, int32_t j, const src_rec &r)
-{
-    return (pb.axis[j] ? r.ry : r.rx) < pb.pi[j];
-}
+// Side of a target record: lo iff its coordinate is below the pivot coordinate.
 __device__ __forceinline__ bool rec_lo(const lb_batch &pb, int32_t j, const pt_rec &r)
 {
     return (pb.axis[j] ? r.y : r.x) < pb.pc[j];
@@ -678,6 +701,163 @@ __global__ void __launch_bounds__(LB_T) k_part_lb(lb_batch pb)
     }
 }
 
+// Source lists: per list (blockIdx.y: 0 x, 1 y) only the segments split across
+// it move (from buffer bit[j] to the other); the tiles of LB_B positions find
+// the segment of each position in an LDS window of the segment starts and
+// skip the positions of segments that stay.  Two launches with a scan of the
+// tile counts between them (no chain of waits between tiles): COUNT writes
+// the tile's number of moving lo records, the second launch places every
+// moving record stably (tile prefix from the scan; LO holds the exclusive
+// prefix over segments of the moving lo counts).
+#define LB_SEGW LB_T // segments of a tile held in LDS (one per thread)
+
+struct ps_list {
+    src_rec *buf0, *buf1;        // the list's two buffers
+    const uint8_t *bit;          // per segment: the buffer holding this list
+    const int32_t *LO;           // exclusive prefix of the moving lo counts
+    int32_t *tcnt;               // per tile: moving lo records (COUNT), then their exclusive prefix
+};
+struct ps_batch {
+    ps_list l[2];
+    const int32_t *start;        // segment starts (nseg + 1)
+    const int32_t *nlo;          // lo count per segment
+    const uint8_t *axis;
+    const int32_t *pi;           // pivot rank in the axis order
+    const int32_t *tseg;         // per tile: the segment holding its first position
+    int64_t n;
+    int32_t nseg, ntiles;
+    int32_t *status;
+};
+
+template <bool COUNT>
+__global__ void __launch_bounds__(LB_T) k_part_src(ps_batch pb)
+{
+    const int q = blockIdx.y; // 0: x list, 1: y list
+    const ps_list &p = pb.l[q];
+    __shared__ int32_t wc[LB_I * (LB_T / WAVE)];
+    // the segments j0, j0 + 1, ... that meet the tile: start, the record data
+    // of their split (pivot rank, axis, buffer bit) and placement (LO, nlo)
+    __shared__ int32_t win[LB_SEGW], wpi[LB_SEGW], wlo[LB_SEGW], wnl[LB_SEGW];
+    __shared__ uint8_t wax[LB_SEGW], wbit[LB_SEGW];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    const int32_t tile = blockIdx.x;
+    const int64_t tb = (int64_t)tile * LB_B, te = min(tb + LB_B, pb.n);
+    const int32_t j0 = min(max(pb.tseg[tile], 0), pb.nseg - 1);
+    {
+        const int32_t jj = j0 + tid;
+        const int32_t v = jj <= pb.nseg ? pb.start[jj] : INT32_MAX;
+        win[tid] = v;
+        if (jj < pb.nseg) {
+            wpi[tid] = pb.pi[jj];
+            wlo[tid] = p.LO[jj];
+            wnl[tid] = pb.nlo[jj];
+            wax[tid] = pb.axis[jj];
+            wbit[tid] = p.bit[jj];
+        }
+        // segments of the window that begin before the tile's end
+        const uint64_t in = __ballot(v < te);
+        if (lane == 0) wc[w] = __popcll(in);
+    }
+    __syncthreads();
+    int32_t nw = 0;
+#pragma unroll
+    for (int q2 = 0; q2 < LB_T / WAVE; ++q2) nw += wc[q2];
+    __syncthreads();
+    // fewer than LB_SEGW segments begin before the tile's end: the window holds
+    // every segment of the tile; else (many small segments) look them up
+    const bool inwin = nw < LB_SEGW;
+    const int64_t base = tb + tid;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+    src_rec r[LB_I];
+    uint64_t mk[LB_I];
+    int32_t sg[LB_I]; // window slot of a moving record (or the segment, outside the window), -1 otherwise
+#pragma unroll
+    for (int i = 0; i < LB_I; ++i) {
+        const int64_t pos = base + (int64_t)i * LB_T;
+        bool lo = false;
+        sg[i] = -1;
+        if (pos < pb.n) {
+            if (inwin) {
+                int32_t a0 = 0, a1 = nw - 1; // the last window entry <= pos
+                while (a0 < a1) {
+                    const int32_t mid = (a0 + a1 + 1) >> 1;
+                    if (win[mid] <= pos) a0 = mid; else a1 = mid - 1;
+                }
+                const int ax = wax[a0];
+                if (ax != q) { // this list moves in the segment
+                    sg[i] = a0;
+                    r[i] = ((wbit[a0] & 1) ? p.buf1 : p.buf0)[pos];
+                    lo = (ax ? r[i].ry : r[i].rx) < wpi[a0];
+                }
+            } else {
+                int32_t a0 = j0, a1 = pb.nseg - 1;
+                while (a0 < a1) {
+                    const int32_t mid = (a0 + a1 + 1) >> 1;
+                    if (pb.start[mid] <= pos) a0 = mid; else a1 = mid - 1;
+                }
+                const int32_t j = a0;
+                const int ax = pb.axis[j];
+                if (ax != q) {
+                    sg[i] = j;
+                    r[i] = ((p.bit[j] & 1) ? p.buf1 : p.buf0)[pos];
+                    lo = (ax ? r[i].ry : r[i].rx) < pb.pi[j];
+                }
+            }
+        }
+        mk[i] = __ballot(lo);
+        if (lane == 0) wc[i * (LB_T / WAVE) + w] = __popcll(mk[i]);
+    }
+    __syncthreads();
+    if (COUNT) {
+        if (w == 0) {
+            int32_t v = wc[lane];
+#pragma unroll
+            for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+            if (lane == 0) p.tcnt[tile] = v;
+        }
+        return;
+    }
+    if (w == 0) {
+        // exclusive scan of the (stripe, wave) counts in stripe-major order
+        const int32_t v = wc[lane];
+        const int32_t inc = wave_incl_scan(v);
+        wc[lane] = inc - v;
+    }
+    __syncthreads();
+    const int32_t carry = p.tcnt[tile]; // moving lo records of the tiles before
+#pragma unroll
+    for (int i = 0; i < LB_I; ++i) {
+        if (sg[i] < 0) continue;
+        const int64_t pos = base + (int64_t)i * LB_T;
+        const int32_t j = sg[i];
+        const bool lo = (mk[i] >> lane) & 1;
+        const int32_t before = carry + wc[i * (LB_T / WAVE) + w] + __popcll(mk[i] & lt);
+        const int32_t st = inwin ? win[j] : pb.start[j];
+        const int32_t LOj = inwin ? wlo[j] : p.LO[j], nlj = inwin ? wnl[j] : pb.nlo[j];
+        const uint8_t bj = inwin ? wbit[j] : p.bit[j];
+        const int32_t rank = before - LOj; // lo records before pos in the segment
+        int64_t dst = lo ? (int64_t)st + rank : (int64_t)st + nlj + (pos - st - rank);
+        dst = dst < 0 ? 0 : (dst >= pb.n ? pb.n - 1 : dst); // never leave the array
+        ((bj & 1) ? p.buf0 : p.buf1)[dst] = r[i];
+    }
+}
+
+// Exclusive scan of the tile counts of both source lists (block q: list q).
+__global__ void __launch_bounds__(1024) k_tile_scan(ps_batch pb)
+{
+    __shared__ int32_t sh[1024 / WAVE];
+    int32_t *c = pb.l[blockIdx.x].tcnt;
+    int32_t carry = 0;
+    for (int32_t c0 = 0; c0 < pb.ntiles; c0 += blockDim.x) {
+        const int32_t k = c0 + threadIdx.x;
+        const int32_t v = k < pb.ntiles ? c[k] : 0;
+        int32_t t;
+        const int32_t ex = block_excl_scan(v, sh, &t);
+        if (k < pb.ntiles) c[k] = carry + ex;
+        carry += t;
+    }
+}
+
 // ------------------------------------------------ subtree in LDS --
 // Evaluation at the sources: once every segment holds at most SUB_S sources,
 // one workgroup takes a segment through all its remaining splits in LDS and
@@ -692,7 +872,8 @@ __global__ void __launch_bounds__(LB_T) k_part_lb(lb_batch pb)
 #define SUB_I (SUB_S / SUB_T)
 
 struct subtree_args {
-    const src_rec *lx, *ly;     // x and y lists after step k0
+    const src_rec *lx[2], *ly[2]; // x and y lists after step k0 (two buffers each)
+    const uint8_t *bx, *by;     // per step-k0 segment: the buffer holding its x / y list
     const double *xs, *ys;      // coordinates by rank
     const int32_t *px;          // original index by x rank
     const int32_t *sst;         // starts of the step-k0 segments (nseg0 + 1)
@@ -722,17 +903,18 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
     const int32_t base = a.sst[g0];
     const int32_t n = min(max(a.sst[g0 + 1] - base, 0), SUB_S);
     for (int i = tid; i < n; i += SUB_T) {
-        const src_rec r = a.lx[base + i];
-        rxl[i] = r.rx;
-        ryl[i] = r.ry;
-        pid[i] = a.px[min(max(r.rx, 0), (int32_t)a.ns - 1)];
+        const src_rec r = a.lx[a.bx[g0] & 1][base + i];
+        const int32_t rmax = (int32_t)a.ns - 1; // ranks index the sorted coordinates
+        rxl[i] = min(max(r.rx, 0), rmax);
+        ryl[i] = min(max(r.ry, 0), rmax);
+        pid[i] = a.px[rxl[i]];
         lst[0][0][i] = (uint16_t)i;
     }
     __syncthreads();
     // the y list of the same points, as local ids
     bool missing = false;
     for (int i = tid; i < n; i += SUB_T) {
-        const int32_t rx = a.ly[base + i].rx;
+        const int32_t rx = a.ly[a.by[g0] & 1][base + i].rx;
         int32_t lo_i = 0, hi_i = n - 1;
         while (lo_i < hi_i) {
             const int32_t mid = (lo_i + hi_i) >> 1;
@@ -881,14 +1063,23 @@ __global__ void k_leaf_keys(const pt_rec *__restrict__ lx, int64_t n, uint64_t *
         vals[i] = (int32_t)i;
     }
 }
-__global__ void k_leaf_keys_src(const src_rec *__restrict__ lx, const int32_t *__restrict__ px, int64_t n,
-                                uint64_t *__restrict__ keys, int32_t *__restrict__ vals)
+// For sources the leaf of position i is found in the leaf starts and the
+// record read from the buffer that holds that leaf's x list.
+__global__ void k_leaf_keys_src(const src_rec *__restrict__ lx0, const src_rec *__restrict__ lx1,
+                                const uint8_t *__restrict__ bx, const int32_t *__restrict__ lst, int32_t nleaf,
+                                const int32_t *__restrict__ px, int64_t n, uint64_t *__restrict__ keys,
+                                int32_t *__restrict__ vals)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        const src_rec r = lx[i];
+        int32_t lo = 0, hi = nleaf - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (lst[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        const src_rec r = ((bx[lo] & 1) ? lx1 : lx0)[i];
         const int64_t v = min(max((int64_t)px[min(max((int64_t)r.rx, (int64_t)0), n - 1)], (int64_t)0), n - 1);
-        keys[v] = (uint64_t)(uint32_t)r.seg;
+        keys[v] = (uint64_t)(uint32_t)lo;
         vals[i] = (int32_t)i;
     }
 }
@@ -1060,13 +1251,23 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     int32_t *hist = WS(int32_t, lay.hist);
     int32_t *bsum = WS(int32_t, lay.bsum);
     int32_t *perm = WS(int32_t, lay.perm), *tperm = nt ? WS(int32_t, lay.tperm) : nullptr;
-    // record lists: [0] x-ordered, [1] y-ordered, [2], [3] partition outputs
-    src_rec *sl[4];
-    pt_rec *tl[4];
-    for (int i = 0; i < 4; ++i) {
-        sl[i] = WS(src_rec, lay.srec) + (int64_t)i * ns;
-        tl[i] = nt ? WS(pt_rec, lay.trec) + (int64_t)i * nt : nullptr;
+    // source lists: x in buffers xb[0], xb[1], y in yb[0], yb[1], with a
+    // buffer bit per segment and list (current and next step); target lists:
+    // [0] x-ordered, [1] y-ordered, [2], [3] partition outputs
+    src_rec *xb[2], *yb[2];
+    for (int i = 0; i < 2; ++i) {
+        xb[i] = WS(src_rec, lay.srec) + (int64_t)i * ns;
+        yb[i] = WS(src_rec, lay.srec) + (int64_t)(2 + i) * ns;
     }
+    uint8_t *bits = WS(uint8_t, lay.sbits);
+    const int64_t bstride = lay.nleaf + 1;
+    uint8_t *bxc = bits, *byc = bits + bstride, *bxn = bits + 2 * bstride, *byn = bits + 3 * bstride;
+    int32_t *nlox = WS(int32_t, lay.seg_nlox), *nloy = WS(int32_t, lay.seg_nloy);
+    int32_t *LOY = WS(int32_t, lay.seg_LOy);
+    int32_t *tsegm = WS(int32_t, lay.stseg);
+    int32_t *tcnt = WS(int32_t, lay.stcnt);
+    pt_rec *tl[4];
+    for (int i = 0; i < 4; ++i) tl[i] = nt ? WS(pt_rec, lay.trec) + (int64_t)i * nt : nullptr;
     int32_t *px = WS(int32_t, lay.srank), *py = px + ns, *rxo = px + 2 * ns, *ryo = px + 3 * ns;
     double *xs = WS(double, lay.scoord), *ys = xs + ns;
     int32_t *sstep = WS(int32_t, lay.sstep), *tstep = WS(int32_t, lay.tstep);
@@ -1086,7 +1287,8 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st));
     CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, st));
     k_rank_inv<<<nblk256(ns), 256, 0, st>>>(px, py, ns, rxo, ryo);
-    k_srec_init<<<nblk256(ns), 256, 0, st>>>(px, py, rxo, ryo, ns, sl[0], sl[1]);
+    k_srec_init<<<nblk256(ns), 256, 0, st>>>(px, py, rxo, ryo, ns, xb[0], yb[0]);
+    k_fill_u8<<<1, 64, 0, st>>>(bxc, 2 * bstride); // the root: both lists in buffer 0
     if (nt) {
         CK(presort(a.tgt, nt, 0, k0s, k1, v0, v1, hist, bsum, tperm, nullptr, st));
         k_trec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[0]);
@@ -1109,8 +1311,12 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         const int32_t nseg = (int32_t)(((int64_t)1) << k);
         if (k == k0) {
             subtree_args ta;
-            ta.lx = sl[0];
-            ta.ly = sl[1];
+            ta.lx[0] = xb[0];
+            ta.lx[1] = xb[1];
+            ta.ly[0] = yb[0];
+            ta.ly[1] = yb[1];
+            ta.bx = bxc;
+            ta.by = byc;
             ta.xs = xs;
             ta.ys = ys;
             ta.px = px;
@@ -1136,7 +1342,11 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         const bool even = (k % 2) == 0;
         const int l = k / 2;
         seg_args sa;
-        sa.slx = sl[0]; sa.sly = sl[1];
+        sa.slx[0] = xb[0]; sa.slx[1] = xb[1];
+        sa.sly[0] = yb[0]; sa.sly[1] = yb[1];
+        sa.bx = bxc; sa.by = byc; sa.bx_next = bxn; sa.by_next = byn;
+        sa.nlox = nlox; sa.nloy = nloy;
+        sa.tseg = split ? tsegm : nullptr;
         sa.xs = xs; sa.ys = ys;
         sa.tlx = tl[0]; sa.tly = tl[1];
         sa.sst = sstep + soff_k; sa.tst = tstep + soff_k;
@@ -1153,22 +1363,38 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         k_seg<<<nblk256(nseg), 256, 0, st>>>(sa);
         CK(hipGetLastError());
         if (!split) break;
-        // exclusive scans of the lo counts over segments
-        CK(fmm_scan_i32(nlo, LO, nseg, nullptr, hist, st));
+        // exclusive scans of the lo counts of the moving source lists (and the
+        // targets' lo counts) over segments
+        CK(fmm_scan_i32(nlox, LO, nseg, nullptr, hist, st));
+        CK(fmm_scan_i32(nloy, LOY, nseg, nullptr, hist, st));
         if (nt) CK(fmm_scan_i32(tlo, TLO, nseg, nullptr, hist, st));
-        lb_batch pb;
-        pb.axis = axis; pb.pc = pc; pb.pi = pi; pb.status = a.status;
-        for (int q = 0; q < 2; ++q) {
-            lb_list &p = pb.l[q];
-            p.in = sl[q]; p.out = sl[2 + q];
-            p.state = lbst + (int64_t)q * lay.lbtiles;
-            p.ticket = ticket + q;
-            p.start = sstep + soff_k; p.nlo = nlo; p.LO = LO;
-            p.n = ns; p.nseg = nseg; p.ntiles = st_tiles;
+        {
+            ps_batch pb;
+            for (int q = 0; q < 2; ++q) {
+                ps_list &p = pb.l[q];
+                p.buf0 = q ? yb[0] : xb[0];
+                p.buf1 = q ? yb[1] : xb[1];
+                p.bit = q ? byc : bxc;
+                p.LO = q ? LOY : LO;
+                p.tcnt = tcnt + (int64_t)q * (st_tiles + 1);
+            }
+            pb.start = sstep + soff_k;
+            pb.nlo = nlo;
+            pb.axis = axis;
+            pb.pi = pi;
+            pb.tseg = tsegm;
+            pb.n = ns;
+            pb.nseg = nseg;
+            pb.ntiles = st_tiles;
+            pb.status = a.status;
+            k_part_src<true><<<dim3((unsigned)st_tiles, 2), LB_T, 0, st>>>(pb);
+            k_tile_scan<<<2, 1024, 0, st>>>(pb);
+            k_part_src<false><<<dim3((unsigned)st_tiles, 2), LB_T, 0, st>>>(pb);
+            CK(hipGetLastError());
         }
-        k_part_lb<src_rec><<<dim3((unsigned)st_tiles, 2), LB_T, 0, st>>>(pb);
-        CK(hipGetLastError());
         if (nt) {
+            lb_batch pb;
+            pb.axis = axis; pb.pc = pc; pb.pi = pi; pb.status = a.status;
             for (int q = 0; q < 2; ++q) {
                 lb_list &p = pb.l[q];
                 p.in = tl[q]; p.out = tl[2 + q];
@@ -1179,18 +1405,21 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
             }
             k_part_lb<pt_rec><<<dim3((unsigned)tt_tiles, 2), LB_T, 0, st>>>(pb);
             CK(hipGetLastError());
+            for (int q = 0; q < 2; ++q) {
+                pt_rec *u = tl[q]; tl[q] = tl[2 + q]; tl[2 + q] = u;
+            }
         }
-        for (int q = 0; q < 2; ++q) {
-            src_rec *t = sl[q]; sl[q] = sl[2 + q]; sl[2 + q] = t;
-            if (nt) { pt_rec *u = tl[q]; tl[q] = tl[2 + q]; tl[2 + q] = u; }
-        }
+        uint8_t *tb = bxc; bxc = bxn; bxn = tb;
+        tb = byc; byc = byn; byn = tb;
         soff_k += nseg + 1;
     }
     // leaf order with ascending original index inside every leaf: a stable
     // sort of the identity by leaf number
     const int passes = (2 * L + 7) / 8;
     if (k0 < 0) {
-        k_leaf_keys_src<<<nblk256(ns), 256, 0, st>>>(sl[0], px, ns, k0s, v0);
+        // (the last step left the leaf starts at step 2L and their bits in bxc)
+        k_leaf_keys_src<<<nblk256(ns), 256, 0, st>>>(xb[0], xb[1], bxc, sstep + soff_k, (int32_t)nbox(L), px, ns,
+                                                     k0s, v0);
         if (passes > 0) CK(radix_sort(ns, passes, k0s, k1, v0, v1, hist, bsum, perm, st));
         else CK(hipMemcpyAsync(perm, v0, (size_t)ns * 4, hipMemcpyDeviceToDevice, st));
     }

@@ -66,6 +66,9 @@ TREE_CASES = [
     ("circle_targets", "circle", 5_000, 3, ("circle", 5_003, 72)),
     ("normal_L0", "normal", 333, 0, None),
     ("layer_L1_targets", "layer", 50, 1, ("uniform", 7, 73)),
+    # deep levels with separate targets: every split runs as a global step and
+    # the last ones cut tiles into hundreds of segments of a few sources
+    ("dense_L5_targets", "uniform", 5_000, 5, ("uniform", 300, 75)),
 ]
 
 
