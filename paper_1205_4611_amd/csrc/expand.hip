@@ -644,18 +644,14 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, const double *Sop, 
     int32_t e = e0 + 16 * w;
     if (e < e1) {
         int32_t sb1 = (e + step + pr < e1) ? wl[e + step + pr] : 0;
-        m2l_chunk16<KS> cur;
-        m2l_fetch16<KS, LOG>(a, bo, nbl, e, e1, (e + pr < e1) ? wl[e + pr] : 0, pr, kq, cur);
+        int32_t sb0 = (e + pr < e1) ? wl[e + pr] : 0;
         for (; e < e1; e += step) {
-            // prefetch: the list entry two chunks ahead, the operands of the next
-            const int32_t en = e + step;
-            const int32_t sb2 = (en + step + pr < e1) ? wl[en + step + pr] : 0;
-            m2l_chunk16<KS> nxt;
-            m2l_fetch16<KS, LOG>(a, bo, nbl, en, e1, sb1, pr, kq, nxt);
-            sb1 = sb2;
+            m2l_chunk16<KS> cur;
+            m2l_fetch16<KS, LOG>(a, bo, nbl, e, e1, sb0, pr, kq, cur);
+            sb0 = sb1;
+            sb1 = (e + 2 * step + pr < e1) ? wl[e + 2 * step + pr] : 0;
             const int ksn = min(max((cur.qc + 3) >> 2, 1), KS), mtn = min((cur.qc >> 4) + 1, MT);
             m2l64_pick<MT, KS, LOG, MT, KS>(mtn, ksn, Sl, Il, cur, cT, kq, re, im);
-            cur = nxt;
         }
     }
     // sum over the 16 pairs of a tile (lane bits 0..3)
