@@ -154,7 +154,8 @@ hipError_t fmm_scan_i32(const int32_t *in, int32_t *out, int64_t n, const int32_
 // the (coordinate, index) order the split rule asks for.
 __global__ void k_fill_u8(uint8_t *p, int64_t n)
 {
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
@@ -464,6 +465,8 @@ struct seg_args {
     uint8_t *bx_next, *by_next;   // the same for the next step's segments
     int32_t *nlox, *nloy;         // lo counts of the lists that move (0 where a list stays)
     int32_t *tseg;                // per partition tile: the segment holding its first position, or NULL
+    int32_t ntiles;               // tiles of the source lists
+    int32_t *LOx, *LOy, *TLO;     // exclusive scans of nlox, nloy, tlo when one block holds every segment, else NULL
     const double *xs, *ys;        // source coordinates by rank
     const pt_rec *tlx, *tly;      // target lists (nt > 0)
     const int32_t *sst, *tst;     // step starts (nseg+1)
@@ -484,12 +487,8 @@ struct seg_args {
 // geometry (on even steps), split axis, pivot (the record at rank floor(n/2)
 // of the axis list) and the number of targets below the pivot coordinate.
 // The grid also zeroes the tile states of this step's partition.
-__global__ void k_seg(seg_args a)
+__device__ __forceinline__ void seg_work(const seg_args &a, int32_t j, int32_t &nlx, int32_t &nly, int32_t &tlv)
 {
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t i = gt; i < a.lb_n; i += (int64_t)gridDim.x * blockDim.x) a.lb_clear[i] = 0;
-    const int32_t j = (int32_t)gt;
-    if (j >= a.nseg) return;
     const int32_t s0 = a.sst[j], s1 = a.sst[j + 1];
     const int32_t n = s1 - s0;
     const int32_t t0 = a.nt ? a.tst[j] : 0, t1 = a.nt ? a.tst[j + 1] : 0;
@@ -551,10 +550,11 @@ __global__ void k_seg(seg_args a)
     a.nlo[j] = nl;
     a.tlo[j] = tl;
     // the list along the axis stays; the other moves to the other buffer
-    a.nlox[j] = ax ? nl : 0;
-    a.nloy[j] = ax ? 0 : nl;
-    if (a.tseg) // tiles whose first position lies in [s0, s1)
-        for (int64_t t = ((int64_t)s0 + LB_B - 1) / LB_B; t * LB_B < s1; ++t) a.tseg[t] = j;
+    nlx = ax ? nl : 0;
+    nly = ax ? 0 : nl;
+    tlv = tl;
+    a.nlox[j] = nlx;
+    a.nloy[j] = nly;
     const uint8_t nbx = ax ? (uint8_t)(1 - (a.bx[j] & 1)) : a.bx[j];
     const uint8_t nby = ax ? a.by[j] : (uint8_t)(1 - (a.by[j] & 1));
     a.bx_next[2 * j] = nbx;
@@ -568,6 +568,43 @@ __global__ void k_seg(seg_args a)
         a.tst_next[2 * j] = t0;
         a.tst_next[2 * j + 1] = t0 + tl;
         if (j == a.nseg - 1) a.tst_next[2 * a.nseg] = t1;
+    }
+}
+
+// One thread per segment (seg_work), per tile of the source lists the segment
+// of its first position, the clearing of the targets' partition states, and,
+// when one block holds every segment, the exclusive scans of the lo counts.
+__global__ void __launch_bounds__(1024) k_seg(seg_args a)
+{
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gt; i < a.lb_n; i += stride) a.lb_clear[i] = 0;
+    if (a.tseg)
+        for (int64_t t = gt; t < a.ntiles; t += stride) {
+            const int64_t pos = t * LB_B;
+            int32_t lo = 0, hi = a.nseg - 1; // the last segment starting at or before pos
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (a.sst[mid] <= pos) lo = mid; else hi = mid - 1;
+            }
+            a.tseg[t] = lo;
+        }
+    const int32_t j = (int32_t)gt;
+    int32_t nlx = 0, nly = 0, tlv = 0;
+    if (j < a.nseg) seg_work(a, j, nlx, nly, tlv);
+    if (a.LOx) {
+        __shared__ int32_t sh[1024 / WAVE];
+        int32_t t;
+        const int32_t ex = block_excl_scan(nlx, sh, &t);
+        const int32_t ey = block_excl_scan(nly, sh, &t);
+        if (j < a.nseg) {
+            a.LOx[j] = ex;
+            a.LOy[j] = ey;
+        }
+        if (a.TLO) {
+            const int32_t et = block_excl_scan(tlv, sh, &t);
+            if (j < a.nseg) a.TLO[j] = et;
+        }
     }
 }
 
@@ -1288,7 +1325,7 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, st));
     k_rank_inv<<<nblk256(ns), 256, 0, st>>>(px, py, ns, rxo, ryo);
     k_srec_init<<<nblk256(ns), 256, 0, st>>>(px, py, rxo, ryo, ns, xb[0], yb[0]);
-    k_fill_u8<<<1, 64, 0, st>>>(bxc, 2 * bstride); // the root: both lists in buffer 0
+    k_fill_u8<<<nblk256(2 * bstride), 256, 0, st>>>(bxc, 2 * bstride); // the root: both lists in buffer 0
     if (nt) {
         CK(presort(a.tgt, nt, 0, k0s, k1, v0, v1, hist, bsum, tperm, nullptr, st));
         k_trec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[0]);
@@ -1347,6 +1384,11 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         sa.bx = bxc; sa.by = byc; sa.bx_next = bxn; sa.by_next = byn;
         sa.nlox = nlox; sa.nloy = nloy;
         sa.tseg = split ? tsegm : nullptr;
+        sa.ntiles = st_tiles;
+        const bool fuse = split && nseg <= 1024; // one block holds every segment: scans in k_seg
+        sa.LOx = fuse ? LO : nullptr;
+        sa.LOy = fuse ? LOY : nullptr;
+        sa.TLO = fuse && nt ? TLO : nullptr;
         sa.xs = xs; sa.ys = ys;
         sa.tlx = tl[0]; sa.tly = tl[1];
         sa.sst = sstep + soff_k; sa.tst = tstep + soff_k;
@@ -1360,14 +1402,17 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         sa.lb_clear = split ? lbst : nullptr;
         sa.lb_n = split ? lb_n : 0;
         sa.nseg = nseg; sa.ns = ns; sa.nt = nt;
-        k_seg<<<nblk256(nseg), 256, 0, st>>>(sa);
+        if (fuse) k_seg<<<1, 1024, 0, st>>>(sa);
+        else k_seg<<<nblk256(nseg), 256, 0, st>>>(sa);
         CK(hipGetLastError());
         if (!split) break;
         // exclusive scans of the lo counts of the moving source lists (and the
         // targets' lo counts) over segments
-        CK(fmm_scan_i32(nlox, LO, nseg, nullptr, hist, st));
-        CK(fmm_scan_i32(nloy, LOY, nseg, nullptr, hist, st));
-        if (nt) CK(fmm_scan_i32(tlo, TLO, nseg, nullptr, hist, st));
+        if (!fuse) {
+            CK(fmm_scan_i32(nlox, LO, nseg, nullptr, hist, st));
+            CK(fmm_scan_i32(nloy, LOY, nseg, nullptr, hist, st));
+            if (nt) CK(fmm_scan_i32(tlo, TLO, nseg, nullptr, hist, st));
+        }
         {
             ps_batch pb;
             for (int q = 0; q < 2; ++q) {
