@@ -189,10 +189,13 @@ int fmm2d_get_topology(fmm2d_handle *h, fmm2d_topology *out);
 
 /* Per-phase statistics of the last evaluation (synchronises the stream it
  * ran on).  Times are device milliseconds, recorded only with
- * FMM2D_FLAG_TIMING (else -1). */
+ * FMM2D_FLAG_TIMING (else -1).  FMM2D_PH_P2P is the near-field kernel alone
+ * (P2P, M2P, L2P and the output of every light leaf, the unit partials of
+ * heavy ones); FMM2D_PH_NREDUCE sums the heavy leaves' partials and writes
+ * their output. */
 enum {
     FMM2D_PH_TREE = 0, FMM2D_PH_LISTS, FMM2D_PH_P2M, FMM2D_PH_M2M,
-    FMM2D_PH_PORDER, FMM2D_PH_M2L, FMM2D_PH_L2L, FMM2D_PH_P2L, FMM2D_PH_P2P, FMM2D_NPHASE
+    FMM2D_PH_PORDER, FMM2D_PH_M2L, FMM2D_PH_L2L, FMM2D_PH_P2L, FMM2D_PH_P2P, FMM2D_PH_NREDUCE, FMM2D_NPHASE
 };
 typedef struct fmm2d_stats {
     float ms[FMM2D_NPHASE];

@@ -384,8 +384,10 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_L2L], st));
     HIPCHK(h, fmm_p2l(ea, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2L], st));
-    HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, st));
+    HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 0, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2P], st));
+    HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 1, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_NREDUCE], st));
 
     h->timing_valid = timing;
     h->last_stream = st;

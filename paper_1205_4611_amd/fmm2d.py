@@ -22,7 +22,7 @@ PORDER = {"fixed": 0, "learned": 1, "given": 2}
 FLAG_TIMING = 1
 FLAG_REQUIRE_MODEL = 2
 FLAG_LEAF_SWAP = 4
-PHASES = ("tree", "lists", "p2m", "m2m", "porder", "m2l", "l2l", "p2l", "p2p")
+PHASES = ("tree", "lists", "p2m", "m2m", "porder", "m2l", "l2l", "p2l", "p2p", "near_reduce")
 
 # learned order (see include/fmm2d.h)
 PORDER_SCHEMA = 1
@@ -60,7 +60,7 @@ class Topology(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_float * 9), ("n_weak", ctypes.c_int64),
+    _fields_ = [("ms", ctypes.c_float * 10), ("n_weak", ctypes.c_int64),
                 ("n_strong", ctypes.c_int64), ("n_m2p", ctypes.c_int64), ("n_p2l", ctypes.c_int64),
                 ("n_p2p_pairs", ctypes.c_int64), ("n_m2p_evals", ctypes.c_int64),
                 ("n_p2l_evals", ctypes.c_int64),
