@@ -17,7 +17,10 @@
  *    stored as {x, y}.  All data pointers are DEVICE pointers unless stated.
  *  - Every call that takes `stream` (a hipStream_t, may be NULL for the null
  *    stream) is asynchronous on that stream; the library never synchronises
- *    it except in fmm2d_get_stats / fmm2d_sync.
+ *    it except in fmm2d_get_stats / fmm2d_sync.  fmm2d_eval without
+ *    FMM2D_FLAG_TIMING also runs part of its work on a stream the handle owns
+ *    (default priority), forked from and joined back into `stream` with
+ *    events: when the last kernel on `stream` has finished, all of it has.
  *  - The library never allocates device memory on the evaluation path: the
  *    caller supplies a workspace sized by fmm2d_workspace_size.
  *  - Return value: 0 on success, a negative FMM2D_E* code otherwise; the
@@ -73,7 +76,10 @@ extern "C" {
                              (fmm2d_set_pair_orders) */
 
 /* ---- flags ------------------------------------------------------------ */
-#define FMM2D_FLAG_TIMING 1u        /* record per-phase device times (events) */
+#define FMM2D_FLAG_TIMING 1u        /* record per-phase device times (events); the
+                                       phases then run one after another on the
+                                       caller's stream, without the overlap of the
+                                       far field with the lists and near field */
 #define FMM2D_FLAG_REQUIRE_MODEL 2u /* learned order without a model is an error */
 #define FMM2D_FLAG_LEAF_SWAP 4u     /* finest-level strong pairs that pass the theta-
                                        criterion with the radii interchanged (Sec. 2)
@@ -190,9 +196,9 @@ int fmm2d_get_topology(fmm2d_handle *h, fmm2d_topology *out);
 /* Per-phase statistics of the last evaluation (synchronises the stream it
  * ran on).  Times are device milliseconds, recorded only with
  * FMM2D_FLAG_TIMING (else -1).  FMM2D_PH_P2P is the near-field kernel alone
- * (P2P, M2P, L2P and the output of every light leaf, the unit partials of
- * heavy ones); FMM2D_PH_NREDUCE sums the heavy leaves' partials and writes
- * their output. */
+ * (the P2P and M2P sums of every target: per light leaf, or per unit of a
+ * heavy leaf's list); FMM2D_PH_NREDUCE adds a heavy leaf's unit sums and, for
+ * every target, L2P and the output. */
 enum {
     FMM2D_PH_TREE = 0, FMM2D_PH_LISTS, FMM2D_PH_P2M, FMM2D_PH_M2M,
     FMM2D_PH_PORDER, FMM2D_PH_M2L, FMM2D_PH_L2L, FMM2D_PH_P2L, FMM2D_PH_P2P, FMM2D_PH_NREDUCE, FMM2D_NPHASE

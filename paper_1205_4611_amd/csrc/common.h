@@ -69,6 +69,7 @@ struct fmm_layout {
     // offsets (bytes)
     size_t keys[2], vals[2];     // radix sort ping-pong (max(ns,nt) each)
     size_t hist;                 // radix histogram / scan block sums
+    size_t hist2;                // radix histogram of the y presort when it runs beside the x one
     size_t srec, trec;           // 4 x n records (x- and y-ordered lists, ping-pong)
     size_t srank;                // x and y presort orders, x and y rank of every source (4 ns)
     size_t scoord;               // source x and y coordinates in sorted order (2 ns)
@@ -100,6 +101,7 @@ struct fmm_layout {
     size_t hs, hoff, hbox, hpart; // M2L heavy-box segments (counts, offsets, box, partials)
     size_t nhw, nhoff, nuleaf, npart; // near-field units of heavy leaves
     int64_t nucap;               // capacity in near-field units
+    size_t nsum;                 // near sums per leaf-order target: Phi' [n], then Phi [n] (double2)
     int64_t hmax;                // capacity in segments
     size_t qw;                   // uint8 order per weak pair, weak-list order
     size_t sw, sp;               // weak pairs sorted by order within a box: source, order
@@ -123,6 +125,10 @@ struct fmm_tree_args {
     int32_t *status;              // device status word
     int cap;
     int swap;                     // leaf-level swapped criterion (P2L / M2P)
+    // side stream (or NULL): the y presort runs there beside the x presort,
+    // forked and joined with the two events
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
 };
 // Builds perm/tperm, per-level starts, centres, radii and lists; gathers the
 // sources (with strengths) and targets into leaf order.

@@ -14,6 +14,10 @@ struct fmm2d_handle {
     int32_t *d_status;      // device status word
     double *d_binom;        // [FMM_BN][FMM_BN]
     hipEvent_t ev[FMM2D_NPHASE + 1];
+    // side stream and its fork / join events: y presort (0, 1), tree done (2),
+    // leaf multipoles done (3), lists and plans done (4), far field done (5)
+    hipStream_t side;
+    hipEvent_t sev[6];
     int timing_valid;
     hipStream_t last_stream;
     // learned order model (device copy, owned) and caller-given orders (not owned)
@@ -102,6 +106,7 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->vals[0] = take(4 * nmax);
     lay->vals[1] = take(4 * nmax);
     lay->hist = take(4 * (hist_n > seg_scan_n ? hist_n : seg_scan_n));
+    lay->hist2 = take(4 * hist_n);
     {
         int64_t a = fmm_scan_blocks(hist_n) + 1;
         int64_t b = 4 * (fmm_scan_blocks(nmax) + 1);
@@ -172,6 +177,7 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->nhoff = take(4 * (lay->nleaf + 2));
     lay->nuleaf = take(4 * lay->nucap);
     lay->npart = take(8 * 4 * 64 * lay->nucap);
+    lay->nsum = take(32 * (nt ? nt : ns));
     lay->qw = learned ? take(lay->listcap) : 0;
     lay->sw = learned ? take(4 * lay->listcap) : 0;
     lay->pbox = learned ? take(4 * lay->listcap) : 0;
@@ -207,6 +213,8 @@ extern "C" int fmm2d_create(fmm2d_handle **out, int device)
         free(t);
     }
     for (int i = 0; i <= FMM2D_NPHASE && e == hipSuccess; ++i) e = hipEventCreate(&h->ev[i]);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&h->sev[i], hipEventDisableTiming);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) {
         fmm2d_destroy(h);
@@ -224,6 +232,9 @@ extern "C" void fmm2d_destroy(fmm2d_handle *h)
     (void)hipSetDevice(h->device);
     for (int i = 0; i <= FMM2D_NPHASE; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+    for (int i = 0; i < 6; ++i)
+        if (h->sev[i]) (void)hipEventDestroy(h->sev[i]);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->d_status) (void)hipFree(h->d_status);
     if (h->d_binom) (void)hipFree(h->d_binom);
     if (h->d_model) (void)hipFree(h->d_model);
@@ -339,6 +350,12 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(h, hipSetDevice(h->device));
     const bool timing = (opts->flags & FMM2D_FLAG_TIMING) != 0;
+    // Without timing the far field (P2M ... P2L) and the y presort run on the
+    // handle's side stream, beside the lists and the near field; the output
+    // kernel waits for both.  With timing every phase runs in order on st, so
+    // that the events between them measure one phase each.
+    const bool fork = !timing;
+    hipStream_t sb = fork ? h->side : st;
     k_zero_status<<<1, 16, 0, st>>>(h->d_status);
     if (timing) HIPCHK(h, hipEventRecord(h->ev[0], st));
 
@@ -347,45 +364,73 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     ta.ns = n_src; ta.nt = nt; ta.L = L; ta.theta = opts->theta;
     ta.src = src; ta.tgt = tgt; ta.ws = w; ta.lay = &lay; ta.status = h->d_status; ta.cap = cap;
     ta.swap = (opts->flags & FMM2D_FLAG_LEAF_SWAP) != 0;
+    ta.side = fork ? h->side : nullptr;
+    ta.ev_fork = h->sev[0];
+    ta.ev_join = h->sev[1];
     HIPCHK(h, fmm_build_tree(ta, m, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_TREE], st));
-    HIPCHK(h, fmm_build_lists(ta, st));
-    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_LISTS], st));
 
     fmm_eval_args ea;
     ea.L = L; ea.p = p; ea.kernel = (int)opts->kernel; ea.mixed = mixed;
     ea.ns = n_src; ea.nt = nt ? nt : n_src; ea.at_sources = nt == 0;
     ea.ws = w; ea.lay = &lay; ea.binom = h->d_binom; ea.cap = cap; ea.swap = ta.swap;
     ea.porder = use_model || use_given;
-    HIPCHK(h, fmm_m2l_plan(ea, st));
-    HIPCHK(h, fmm_near_plan(ea, st));
-    HIPCHK(h, fmm_p2m(ea, st));
-    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], st));
-    HIPCHK(h, fmm_m2m(ea, st));
-    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2M], st));
-    if (ea.porder) {
-        fmm_porder_args pa = porder_args(h, w, lay, L, p, cap);
-        if (use_model) {
+    fmm_porder_args pa = porder_args(h, w, lay, L, p, cap);
+    if (use_model) {
+        pa.model = h->d_model;
+        pa.delta = h->delta;
+    } else {
+        pa.given = h->given;
+        pa.ngiven = h->ngiven;
+    }
+    // the multipoles, upward pass and coefficient norms need the tree only
+    auto upward = [&]() -> int {
+        HIPCHK(h, fmm_p2m(ea, sb));
+        if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], sb));
+        if (fork) HIPCHK(h, hipEventRecord(h->sev[3], sb));
+        HIPCHK(h, fmm_m2m(ea, sb));
+        if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2M], sb));
+        if (use_model)
             HIPCHK(h, fmm_box_norms(reinterpret_cast<const double2 *>(w + lay.A), pa.radius, p, lay.nb,
                                     reinterpret_cast<double *>(w + lay.n1), reinterpret_cast<double *>(w + lay.tail),
-                                    st));
-            pa.model = h->d_model;
-            pa.delta = h->delta;
-        } else {
-            pa.given = h->given;
-            pa.ngiven = h->ngiven;
-        }
-        HIPCHK(h, fmm_porder(pa, st));
+                                    sb));
+        return 0;
+    };
+    // orders, M2L, downward pass and P2L need the lists too
+    auto downward = [&]() -> int {
+        if (ea.porder) HIPCHK(h, fmm_porder(pa, sb));
+        if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_PORDER], sb));
+        HIPCHK(h, fmm_m2l(ea, sb));
+        if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2L], sb));
+        HIPCHK(h, fmm_l2l(ea, sb));
+        if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_L2L], sb));
+        HIPCHK(h, fmm_p2l(ea, sb));
+        if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2L], sb));
+        return 0;
+    };
+    int rc2 = 0;
+    if (fork) {
+        HIPCHK(h, hipEventRecord(h->sev[2], st));
+        HIPCHK(h, hipStreamWaitEvent(sb, h->sev[2], 0));
+        if ((rc2 = upward())) return rc2;
     }
-    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_PORDER], st));
-    HIPCHK(h, fmm_m2l(ea, st));
-    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2L], st));
-    HIPCHK(h, fmm_l2l(ea, st));
-    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_L2L], st));
-    HIPCHK(h, fmm_p2l(ea, st));
-    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2L], st));
+    HIPCHK(h, fmm_build_lists(ta, st));
+    if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_LISTS], st));
+    HIPCHK(h, fmm_m2l_plan(ea, st));
+    HIPCHK(h, fmm_near_plan(ea, st));
+    if (fork) {
+        HIPCHK(h, hipEventRecord(h->sev[4], st));
+        HIPCHK(h, hipStreamWaitEvent(sb, h->sev[4], 0));
+        if ((rc2 = downward())) return rc2;
+        HIPCHK(h, hipEventRecord(h->sev[5], sb));
+        HIPCHK(h, hipStreamWaitEvent(st, h->sev[3], 0)); // M2P reads the leaf multipoles
+    } else {
+        if ((rc2 = upward())) return rc2;
+        if ((rc2 = downward())) return rc2;
+    }
     HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 0, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2P], st));
+    if (fork) HIPCHK(h, hipStreamWaitEvent(st, h->sev[5], 0)); // L2P reads the local expansions
     HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 1, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_NREDUCE], st));
 

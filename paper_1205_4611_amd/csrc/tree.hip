@@ -1320,9 +1320,23 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
     int32_t *ticket = reinterpret_cast<int32_t *>(lbst + 4 * lay.lbtiles);
     const int64_t lb_n = 4 * lay.lbtiles + 2;
 
-    // presort into (coordinate, index) order; source records of ranks
-    CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st));
-    CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, st));
+    // presort into (coordinate, index) order; source records of ranks.  With
+    // a side stream the y presort runs there, beside the x one, in the record
+    // buffers (2 x 8 + 2 x 4 bytes per source of their 32, unused until the
+    // records are built) with a histogram of its own.
+    if (a.side) {
+        uint64_t *ky0 = WS(uint64_t, lay.srec), *ky1 = ky0 + ns;
+        int32_t *vy0 = reinterpret_cast<int32_t *>(ky1 + ns), *vy1 = vy0 + ns;
+        CK(hipEventRecord(a.ev_fork, st));
+        CK(hipStreamWaitEvent(a.side, a.ev_fork, 0));
+        CK(presort(a.src, ns, 1, ky0, ky1, vy0, vy1, WS(int32_t, lay.hist2), bsum, py, ys, a.side));
+        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st));
+        CK(hipEventRecord(a.ev_join, a.side));
+        CK(hipStreamWaitEvent(st, a.ev_join, 0));
+    } else {
+        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st));
+        CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, st));
+    }
     k_rank_inv<<<nblk256(ns), 256, 0, st>>>(px, py, ns, rxo, ryo);
     k_srec_init<<<nblk256(ns), 256, 0, st>>>(px, py, rxo, ryo, ns, xb[0], yb[0]);
     k_fill_u8<<<nblk256(2 * bstride), 256, 0, st>>>(bxc, 2 * bstride); // the root: both lists in buffer 0
