@@ -137,6 +137,10 @@ int fmm2d_workspace_size(fmm2d_handle *h, int64_t n_src, int64_t n_tgt,
  *   ws    device workspace of ws_bytes >= fmm2d_workspace_size(...)
  * Pairs with coincident points (both coordinates equal) are excluded, so a
  * source never acts on itself.  Outputs are in the caller's target order.
+ * The FP64 near field of the harmonic kernel evaluates 1/|w|^2 as
+ * 1/(|w|^2 + 2^-255), four pairs per reciprocal: exact to rounding for point
+ * separations above 2^-100, and it needs near-field separations (neighbouring
+ * leaves) below 2^127.
  * Phi uses the principal Log in every near-field pair; in the far field it
  * follows the branch of Log(c_T - c_S) of the interacting box centres (the
  * log term of eq. (multipole)), so Phi is defined modulo 2 pi i m_j terms.

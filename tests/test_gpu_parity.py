@@ -189,6 +189,40 @@ def test_operating_point_tol(fmm, orc):
     assert nrm(host(gp)[sel], rb) < 1e-8
 
 
+def test_near_duplicates_harmonic(fmm, orc):
+    """Point pairs 1e-12 and 1e-25 apart (the second group next to the origin,
+    where such separations are representable), above the 2^-100 below which
+    the FP64 harmonic near field perturbs 1/|w|^2: the FMM at the sources
+    against the oracle FMM at equal p, pointwise."""
+    rng = np.random.default_rng(93)
+    base = workloads.points("uniform", 3000, 91)
+    ang = np.exp(2j * np.pi * rng.random(300))
+    near0 = 1e-20 * (rng.random(50) + 1j * rng.random(50))
+    src = np.concatenate([base, base[:300] + 1e-12 * ang, near0, near0 + 1e-25 * ang[:50]])
+    m = workloads.strengths(len(src), 94)
+    L = orc.nlevels(len(src), 40)
+    _, gd = fmm.eval(dev(src), dev(m), p=17, levels=L, kernel="harmonic")
+    _, rd = orc.Tree(src, L).eval(m, 17, orc.KERNEL_HARMONIC)
+    rel = np.abs(host(gd) - rd) / np.abs(rd)
+    assert np.max(np.abs(rd[3000:3300])) > 1e11 and np.max(np.abs(rd[3300:])) > 1e24
+    assert float(np.max(rel)) < 1e-9, float(np.max(rel))
+
+
+def test_schedules_agree(fmm):
+    """The timed schedule (phases in order on one stream) and the default one
+    (far field on the side stream) run the same kernels on the same data:
+    bit-identical outputs."""
+    src = workloads.points("clusters", 40_000, 95)
+    m = workloads.strengths(40_000, 96)
+    for kernel in ("log", "harmonic"):
+        a = fmm.eval(dev(src), dev(m), p=17, kernel=kernel, swap=True)
+        b = fmm.eval(dev(src), dev(m), p=17, kernel=kernel, swap=True, timing=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a[1], b[1])
+        if kernel == "log":
+            assert torch.equal(a[0], b[0])
+
+
 def test_deterministic(fmm):
     src = workloads.points("clusters", 30_000, 79)
     m = workloads.strengths(30_000, 80)
