@@ -57,7 +57,7 @@ def traffic_bytes():
     kv = {}
     for line in open(TRAFFIC_FILE):
         if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
+            k, v = line.rsplit(":", 1)  # the last colon: a key may hold one ("sha256[:16]")
             kv[k.strip()] = v.strip()
     src = os.path.join(HERE, "paper_1205_4611_amd", "csrc", "p2p.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
