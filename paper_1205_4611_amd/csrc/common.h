@@ -91,6 +91,7 @@ struct fmm_layout {
     size_t mcnt, pcnt, moff, poff, midx, pidx; // finest-level M2P / P2L lists
     int64_t leafcap;             // entries of each M2P / P2L array
     size_t lbsum;                // list scan block sums
+    size_t lhvy, lhcnt;          // list build: heavy boxes per level (level-local ids), their counts
     size_t srcs;                 // double4 sources in leaf order
     size_t tgts;                 // double2 targets in leaf order
     size_t m32;                  // float2 strengths in leaf order (mixed)

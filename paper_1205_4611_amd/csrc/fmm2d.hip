@@ -153,6 +153,8 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->midx = take(4 * lay->leafcap);
     lay->pidx = take(4 * lay->leafcap);
     lay->lbsum = take(4 * (fmm_scan_blocks(lay->nleaf) + 2));
+    lay->lhvy = take(4 * lay->nb);
+    lay->lhcnt = take(4 * (L + 2));
     lay->srcs = take(32 * ns);
     lay->tgts = take(16 * nt);
     lay->m32 = mixed == 1 ? take(8 * ns) : 0;

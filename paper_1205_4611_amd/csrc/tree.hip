@@ -1161,41 +1161,45 @@ struct list_args {
     const int32_t *moff, *poff;    // M2P / P2L offsets (fill pass)
     int32_t *midx_out, *pidx_out;  // M2P / P2L lists (fill pass)
     int32_t lcap;                  // capacity of the M2P / P2L arrays
+    const int32_t *hvy, *hcnt;     // heavy boxes of this level (level-local ids) and their count
+    int32_t *hvy_next, *hcnt_next; // the same for the next level (fill pass appends), or NULL
 };
 
-// One wave per box: the lanes take the candidates (children 4s..4s+3 of the
-// parent's strong boxes, in ascending order) 64 at a time, test them in
-// parallel, and compact each class in order with ballots.  Classes: weak
-// (M2L), strong (next level; P2P at the finest), and at the finest level with
-// the swapped criterion M2P (this box larger) and P2L (candidate larger).
+// A box whose candidate set (4 x its parent's strong count) exceeds
+// LIST_HEAVY is shared by the 4 waves of a workgroup; the first LIST_HB
+// workgroups of a launch take these boxes from the level's heavy list (filled
+// by the previous level's fill pass), the others take one light box per wave.
+// Clustered inputs put a few thousand strong boxes next to a large box, and
+// one wave walking its children's candidates would set the launch's length.
+#define LIST_HEAVY 512
+#define LIST_HB 256
+
+struct list_cnt {
+    int32_t w, s, m, p; // weak, strong, M2P, P2L
+};
+
+__device__ __forceinline__ bool list_heavy(const int32_t *psoff, int32_t b)
+{
+    const int32_t q = b >> 2;
+    return 4 * (psoff[q + 1] - psoff[q]) > LIST_HEAVY;
+}
+
+// Candidates [kb, ke) of box b (candidate k: child k & 3 of the parent's strong
+// entry e0 + k / 4): their class counts and, with FILL, the entries written
+// from the positions in o on, in candidate order (ballot compaction).
+// Classes: weak (M2L), strong (next level; P2P at the finest), and at the
+// finest level with the swapped criterion M2P (this box larger) and P2L
+// (candidate larger).
 template <bool FILL>
-__global__ void __launch_bounds__(256) k_lists(list_args a)
+__device__ __forceinline__ list_cnt list_range(const list_args &a, int32_t b, int32_t e0, int32_t kb, int32_t ke,
+                                               double cbx, double cby, double rb, list_cnt o)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int32_t b = wave_index();
-    if (b >= a.nbl) return;
-    const int32_t q = b >> 2;
-    const int32_t e0 = min(a.psoff[q], a.cap), e1 = min(a.psoff[q + 1], a.cap);
-    const int32_t ncand = 4 * (e1 - e0);
-    const double cbx = a.centre[2 * (int64_t)b], cby = a.centre[2 * (int64_t)b + 1];
-    const double rb = a.radius[b];
-    int32_t wo = 0, so = 0, mo = 0, po = 0;
-    if (FILL) {
-        wo = a.woff[b];
-        so = a.soff[b];
-        bool over = a.woff[b + 1] > a.cap || a.soff[b + 1] > a.cap;
-        if (a.swap) {
-            mo = a.moff[b];
-            po = a.poff[b];
-            over = over || a.moff[b + 1] > a.lcap || a.poff[b + 1] > a.lcap;
-        }
-        if (lane == 0 && over) atomicOr(a.status, FMM_ST_LIST_OVERFLOW);
-    }
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
-    int32_t nw = 0, nsg = 0, nm = 0, np = 0;
-    for (int32_t k0 = 0; k0 < ncand; k0 += WAVE) {
+    list_cnt n = {0, 0, 0, 0};
+    for (int32_t k0 = kb; k0 < ke; k0 += WAVE) {
         const int32_t k = k0 + lane;
-        const bool act = k < ncand;
+        const bool act = k < ke;
         int cls = 1; // 0 weak, 1 strong, 2 M2P, 3 P2L
         int32_t c = 0;
         if (act) {
@@ -1214,31 +1218,131 @@ __global__ void __launch_bounds__(256) k_lists(list_args a)
         const uint64_t mp = __ballot(act && cls == 3);
         if (FILL && act) {
             if (cls == 0) {
-                const int32_t pos = wo + nw + __popcll(mw & lt);
+                const int32_t pos = o.w + n.w + __popcll(mw & lt);
                 if (pos < a.cap) a.widx_out[pos] = c;
             } else if (cls == 1) {
-                const int32_t pos = so + nsg + __popcll(ms & lt);
+                const int32_t pos = o.s + n.s + __popcll(ms & lt);
                 if (pos < a.cap) a.sidx_out[pos] = c;
             } else if (cls == 2) {
-                const int32_t pos = mo + nm + __popcll(mm & lt);
+                const int32_t pos = o.m + n.m + __popcll(mm & lt);
                 if (pos < a.lcap) a.midx_out[pos] = c;
             } else {
-                const int32_t pos = po + np + __popcll(mp & lt);
+                const int32_t pos = o.p + n.p + __popcll(mp & lt);
                 if (pos < a.lcap) a.pidx_out[pos] = c;
             }
         }
-        nw += __popcll(mw);
-        nsg += __popcll(ms);
-        nm += __popcll(mm);
-        np += __popcll(mp);
+        n.w += __popcll(mw);
+        n.s += __popcll(ms);
+        n.m += __popcll(mm);
+        n.p += __popcll(mp);
     }
-    if (!FILL && lane == 0) {
-        a.wcnt[b] = nw;
-        a.scnt[b] = nsg;
-        if (a.swap) {
-            a.mcnt[b] = nm;
-            a.pcnt[b] = np;
+    return n;
+}
+
+// Fill pass: the list starts of box b, with the overflow check.
+__device__ __forceinline__ list_cnt list_starts(const list_args &a, int32_t b, bool &over)
+{
+    list_cnt o = {a.woff[b], a.soff[b], 0, 0};
+    over = a.woff[b + 1] > a.cap || a.soff[b + 1] > a.cap;
+    if (a.swap) {
+        o.m = a.moff[b];
+        o.p = a.poff[b];
+        over = over || a.moff[b + 1] > a.lcap || a.poff[b + 1] > a.lcap;
+    }
+    return o;
+}
+
+// Fill pass: a box whose children will be heavy at the next level enters that
+// level's heavy list (the order of the list does not matter: each box writes
+// its own positions).
+__device__ __forceinline__ void list_next_heavy(const list_args &a, int32_t b, int32_t nstrong)
+{
+    if (a.hvy_next && 4 * nstrong > LIST_HEAVY) {
+        const int32_t pos = atomicAdd(a.hcnt_next, 4);
+        for (int i = 0; i < 4; ++i) a.hvy_next[pos + i] = 4 * b + i;
+    }
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_lists(list_args a)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const list_cnt zero = {0, 0, 0, 0};
+    if ((int32_t)blockIdx.x >= LIST_HB) {
+        // one light box per wave
+        const int32_t b = ((int32_t)blockIdx.x - LIST_HB) * 4 + __builtin_amdgcn_readfirstlane(w);
+        if (b >= a.nbl || list_heavy(a.psoff, b)) return;
+        const int32_t q = b >> 2;
+        const int32_t e0 = min(a.psoff[q], a.cap), e1 = min(a.psoff[q + 1], a.cap);
+        const double cbx = a.centre[2 * (int64_t)b], cby = a.centre[2 * (int64_t)b + 1];
+        const double rb = a.radius[b];
+        list_cnt o = zero;
+        if (FILL) {
+            bool over;
+            o = list_starts(a, b, over);
+            if (lane == 0 && over) atomicOr(a.status, FMM_ST_LIST_OVERFLOW);
         }
+        const list_cnt n = list_range<FILL>(a, b, e0, 0, 4 * (e1 - e0), cbx, cby, rb, o);
+        if (lane == 0) {
+            if (!FILL) {
+                a.wcnt[b] = n.w;
+                a.scnt[b] = n.s;
+                if (a.swap) {
+                    a.mcnt[b] = n.m;
+                    a.pcnt[b] = n.p;
+                }
+            } else {
+                list_next_heavy(a, b, n.s);
+            }
+        }
+        return;
+    }
+    // heavy boxes: the 4 waves take contiguous ranges of 64-candidate chunks
+    __shared__ list_cnt hc[4];
+    const int32_t nh = min(*a.hcnt, a.nbl);
+    for (int32_t h = blockIdx.x; h < nh; h += LIST_HB) {
+        const int32_t b = min(max(a.hvy[h], 0), a.nbl - 1);
+        const int32_t q = b >> 2;
+        const int32_t e0 = min(a.psoff[q], a.cap), e1 = min(a.psoff[q + 1], a.cap);
+        const int32_t ncand = 4 * (e1 - e0);
+        const int32_t C = (ncand + 4 * WAVE - 1) / (4 * WAVE) * WAVE;
+        const int32_t kb = min(w * C, ncand), ke = min(kb + C, ncand);
+        const double cbx = a.centre[2 * (int64_t)b], cby = a.centre[2 * (int64_t)b + 1];
+        const double rb = a.radius[b];
+        const list_cnt n = list_range<false>(a, b, e0, kb, ke, cbx, cby, rb, zero);
+        if (lane == 0) hc[w] = n;
+        __syncthreads();
+        if (!FILL) {
+            if (threadIdx.x == 0) {
+                list_cnt t = zero;
+                for (int v = 0; v < 4; ++v) {
+                    t.w += hc[v].w; t.s += hc[v].s; t.m += hc[v].m; t.p += hc[v].p;
+                }
+                a.wcnt[b] = t.w;
+                a.scnt[b] = t.s;
+                if (a.swap) {
+                    a.mcnt[b] = t.m;
+                    a.pcnt[b] = t.p;
+                }
+            }
+        } else {
+            bool over;
+            list_cnt o = list_starts(a, b, over);
+            int32_t ns = 0;
+            for (int v = 0; v < 4; ++v) {
+                if (v < w) {
+                    o.w += hc[v].w; o.s += hc[v].s; o.m += hc[v].m; o.p += hc[v].p;
+                }
+                ns += hc[v].s;
+            }
+            if (threadIdx.x == 0) {
+                if (over) atomicOr(a.status, FMM_ST_LIST_OVERFLOW);
+                list_next_heavy(a, b, ns);
+            }
+            list_range<true>(a, b, e0, kb, ke, cbx, cby, rb, o);
+        }
+        __syncthreads();
     }
 }
 
@@ -1249,11 +1353,12 @@ __global__ void k_root(int32_t *sstep, int32_t ns, int32_t *tstep, int32_t nt)
     tstep[0] = 0; tstep[1] = nt;
 }
 
-__global__ void k_lists_root(int32_t *woff, int32_t *soff, int32_t *sidx)
+__global__ void k_lists_root(int32_t *woff, int32_t *soff, int32_t *sidx, int32_t *hcnt, int L)
 {
     woff[0] = 0; woff[1] = 0;
     soff[0] = 0; soff[1] = 1;
     sidx[0] = 0;
+    for (int l = 0; l <= L + 1; ++l) hcnt[l] = 0;
 }
 
 __global__ void k_gather(const double *__restrict__ src, const double *__restrict__ m,
@@ -1507,7 +1612,8 @@ hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st)
     int32_t *widx = WS(int32_t, lay.widx), *sidx = WS(int32_t, lay.sidx);
     int32_t *wcnt = WS(int32_t, lay.wcnt), *scnt = WS(int32_t, lay.scnt);
     int32_t *lbsum = WS(int32_t, lay.lbsum);
-    k_lists_root<<<1, 1, 0, st>>>(woff, soff, sidx);
+    int32_t *hvy = WS(int32_t, lay.lhvy), *hcnt = WS(int32_t, lay.lhcnt);
+    k_lists_root<<<1, 1, 0, st>>>(woff, soff, sidx, hcnt, L);
     if (!a.swap) {
         k_fill_i32<<<nblk256(nbox(L) + 1), 256, 0, st>>>(WS(int32_t, lay.moff), nbox(L) + 1, 0);
         k_fill_i32<<<nblk256(nbox(L) + 1), 256, 0, st>>>(WS(int32_t, lay.poff), nbox(L) + 1, 0);
@@ -1534,7 +1640,12 @@ hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st)
         la.midx_out = WS(int32_t, lay.midx);
         la.pidx_out = WS(int32_t, lay.pidx);
         la.lcap = (int32_t)lay.leafcap;
-        const unsigned nwb = (unsigned)((nbox(l) + 3) / 4); // 4 waves (boxes) per block
+        la.hvy = hvy + box_off(l);
+        la.hcnt = hcnt + l;
+        la.hvy_next = l < L ? hvy + box_off(l + 1) : nullptr;
+        la.hcnt_next = l < L ? hcnt + l + 1 : nullptr;
+        // LIST_HB workgroups for the heavy boxes, then 4 light boxes per workgroup
+        const unsigned nwb = (unsigned)(LIST_HB + (nbox(l) + 3) / 4);
         k_lists<false><<<nwb, 256, 0, st>>>(la);
         CK(fmm_scan_i32(wcnt, woff + start_off(l), nbox(l), woff + start_off(l - 1) + nbox(l - 1),
                         lbsum, st));
