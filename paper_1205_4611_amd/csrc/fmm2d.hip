@@ -15,7 +15,7 @@ struct fmm2d_handle {
     double *d_binom;        // [FMM_BN][FMM_BN]
     hipEvent_t ev[FMM2D_NPHASE + 1];
     // side stream and its fork / join events: y presort (0, 1), tree done (2),
-    // leaf multipoles done (3), lists and plans done (4), far field done (5)
+    // M2L done (3), lists and plans done (4), far field done (5)
     hipStream_t side;
     hipEvent_t sev[6];
     int timing_valid;
@@ -389,7 +389,6 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     auto upward = [&]() -> int {
         HIPCHK(h, fmm_p2m(ea, sb));
         if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], sb));
-        if (fork) HIPCHK(h, hipEventRecord(h->sev[3], sb));
         HIPCHK(h, fmm_m2m(ea, sb));
         if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2M], sb));
         if (use_model)
@@ -404,6 +403,7 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
         if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_PORDER], sb));
         HIPCHK(h, fmm_m2l(ea, sb));
         if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2L], sb));
+        if (fork) HIPCHK(h, hipEventRecord(h->sev[3], sb));
         HIPCHK(h, fmm_l2l(ea, sb));
         if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_L2L], sb));
         HIPCHK(h, fmm_p2l(ea, sb));
@@ -425,7 +425,12 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
         HIPCHK(h, hipStreamWaitEvent(sb, h->sev[4], 0));
         if ((rc2 = downward())) return rc2;
         HIPCHK(h, hipEventRecord(h->sev[5], sb));
-        HIPCHK(h, hipStreamWaitEvent(st, h->sev[3], 0)); // M2P reads the leaf multipoles
+        // The near kernel needs only the leaf multipoles (M2P), but it starts
+        // after M2L: M2L waves hold 160 VGPRs and find little room once the
+        // near kernel's 48-VGPR waves fill the CUs, so side by side M2L ran
+        // past the end of the near kernel; alone it runs at full rate, and
+        // L2L and P2L run beside the near kernel.
+        HIPCHK(h, hipStreamWaitEvent(st, h->sev[3], 0));
     } else {
         if ((rc2 = upward())) return rc2;
         if ((rc2 = downward())) return rc2;
