@@ -103,6 +103,30 @@ __device__ __forceinline__ void pair_features(const feat_ctx &c, int64_t gS, flo
     f[7] = lg10_fast((double)(c.nweak > 0 ? c.nweak : 1));
 }
 
+// Sum of n1 over the weak list entries [e0, e1) of a box (the share
+// denominator of feature f6), in every lane: lane i adds entries i, i + 64, ...
+// in order, then a butterfly.  The lane loads 8 entries per round trip (a
+// box's list can hold 16k pairs); padding adds exact zeros.
+__device__ __forceinline__ double box_den(const double *__restrict__ n1, const int32_t *__restrict__ widx, int32_t e0,
+                                          int32_t e1, int64_t bo, int32_t nbl)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    double den = 0.0;
+    for (int32_t e = e0 + lane; e < e1; e += 8 * WAVE) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t eu = e + u * WAVE;
+            v[u] = eu < e1 ? n1[bo + min(max(widx[eu], 0), nbl - 1)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) den += v[u];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) den += __shfl_xor(den, o, WAVE);
+    return den;
+}
+
 // Shared set-up of the wave-per-target-box kernels: the box's weak range and
 // the feature context (the share denominator is a wave reduction).
 __device__ __forceinline__ bool box_setup(const double *centre, const double *radius, const double *n1,
@@ -119,10 +143,7 @@ __device__ __forceinline__ bool box_setup(const double *centre, const double *ra
     e1 = min(woff[so + b + 1], cap);
     if (e0 >= e1) return false;
     nbl = (int32_t)(((int64_t)1) << (2 * l));
-    double den = 0.0;
-    for (int32_t e = e0 + lane; e < e1; e += WAVE) den += n1[bo + min(max(widx[e], 0), nbl - 1)];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) den += __shfl_xor(den, o, WAVE);
+    const double den = box_den(n1, widx, e0, e1, bo, nbl);
     c.centre = centre; c.radius = radius; c.n1 = n1; c.tail = tail;
     c.g = g; c.bo = bo; c.l = l; c.L = L;
     c.n1root = n1[0];
@@ -250,6 +271,12 @@ __global__ void __launch_bounds__(256) k_porder(fmm_porder_args a, const float *
     // per wave: the unit's sources and orders (lane i keeps entries i, i + 64, ...)
     __shared__ int32_t s_src[256 / WAVE][PORDER_RCH * WAVE];
     __shared__ uint8_t s_q[256 / WAVE][PORDER_RCH * WAVE];
+    // the grid covers the capacity in heavy-box segments: a block past the
+    // segments in use returns before it loads the model (block-uniform)
+    {
+        const int64_t t0 = (int64_t)blockIdx.x * (blockDim.x / WAVE);
+        if (t0 >= a.nb && t0 - a.nb >= a.hoff[a.nb]) return;
+    }
     if (model) {
         for (int k = threadIdx.x; k < FMM2D_PORDER_MODEL_FLOATS; k += blockDim.x) smodel[k] = model[k];
         __syncthreads();
@@ -268,10 +295,7 @@ __global__ void __launch_bounds__(256) k_porder(fmm_porder_args a, const float *
         // the whole box's list (a heavy box's segments each sum it, in one order)
         int32_t E0, E1;
         box_range(a.woff, a.L, g, a.cap, l, bo, E0, E1);
-        double den = 0.0;
-        for (int32_t e = E0 + lane; e < E1; e += WAVE) den += a.n1[bo + min(max(a.widx[e], 0), nbl - 1)];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) den += __shfl_xor(den, o, WAVE);
+        const double den = box_den(a.n1, a.widx, E0, E1, bo, nbl);
         const int64_t so = d_start_off(l) + (g - bo);
         c.centre = a.centre; c.radius = a.radius; c.n1 = a.n1; c.tail = a.tail;
         c.g = g; c.bo = bo; c.l = l; c.L = a.L;

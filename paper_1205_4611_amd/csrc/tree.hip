@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
                                                       uint64_t *__restrict__ kout,
                                                       int32_t *__restrict__ vout, int64_t n,
                                                       int shift, const int32_t *__restrict__ off,
-                                                      int nblk)
+                                                      int nblk, int32_t *__restrict__ rank)
 {
     constexpr int NW = RS_T / WAVE, PER_W = RS_BLOCK / NW, IT = PER_W / WAVE;
     __shared__ uint64_t sk[RS_BLOCK];
@@ -326,7 +326,11 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
         int64_t pos = (int64_t)off[(int64_t)d * nblk + blockIdx.x] + (j - dstart[d]);
         pos = pos < 0 ? 0 : (pos >= n ? n - 1 : pos); // never leave the array
         kout[pos] = kk;
-        vout[pos] = sv[j];
+        const int32_t v = sv[j];
+        vout[pos] = v;
+        // last pass of a presort: the values are the original indices, and
+        // pos is the rank of that point
+        if (rank) rank[v < 0 ? 0 : (v >= n ? n - 1 : v)] = (int32_t)pos;
     }
 }
 
@@ -335,9 +339,10 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
 // hist holds 256 * nblk + 256 ints (histograms, scanned in place into the
 // scatter offsets, then the digit totals).
 static hipError_t radix_sort(int64_t n, int passes, uint64_t *k0, uint64_t *k1, int32_t *v0, int32_t *v1,
-                             int32_t *hist, int32_t *bsum, int32_t *out, hipStream_t st)
+                             int32_t *hist, int32_t *bsum, int32_t *out, hipStream_t st, int32_t *rank = nullptr)
 {
     if (n <= 0) return hipSuccess;
+    if (passes <= 0) return hipMemcpyAsync(out, v0, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
     const int nblk = (int)((n + RS_BLOCK - 1) / RS_BLOCK);
     int32_t *off = hist, *tot = hist + (int64_t)256 * nblk;
     uint64_t *ka = k0, *kb = k1;
@@ -347,11 +352,13 @@ static hipError_t radix_sort(int64_t n, int passes, uint64_t *k0, uint64_t *k1, 
         k_rs_hist<<<nblk, RS_T, 0, st>>>(ka, n, shift, hist, nblk);
         k_rs_coltot<<<256, 1024, 0, st>>>(hist, nblk, tot);
         k_rs_offsets<<<256, 1024, 0, st>>>(hist, tot, nblk, off);
-        k_rs_scatter<<<nblk, RS_T, 0, st>>>(ka, va, kb, vb, n, shift, off, nblk);
+        // the last pass writes the values to out (and, given rank, the inverse)
+        const bool last = pass == passes - 1;
+        k_rs_scatter<<<nblk, RS_T, 0, st>>>(ka, va, kb, last ? out : vb, n, shift, off, nblk, last ? rank : nullptr);
         uint64_t *tk = ka; ka = kb; kb = tk;
         int32_t *tv = va; va = vb; vb = tv;
     }
-    return hipMemcpyAsync(out, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+    return hipGetLastError();
 }
 
 // Coordinate of each sorted key: the inverse of order_key, except that -0
@@ -373,15 +380,16 @@ __global__ void k_rs_decode(const uint64_t *__restrict__ keys, const int32_t *__
     }
 }
 
-// Indices 0..n-1 of pts ordered by (coordinate `axis`, index) into out and,
-// if coord is not NULL, the coordinates in that order into coord.
+// Indices 0..n-1 of pts ordered by (coordinate `axis`, index) into out, the
+// inverse (rank of every index) into rank if not NULL and, if coord is not
+// NULL, the coordinates in that order into coord.
 static hipError_t presort(const double *pts, int64_t n, int axis, uint64_t *k0, uint64_t *k1,
                           int32_t *v0, int32_t *v1, int32_t *hist, int32_t *bsum, int32_t *out,
-                          double *coord, hipStream_t st)
+                          double *coord, hipStream_t st, int32_t *rank = nullptr)
 {
     if (n <= 0) return hipSuccess;
     k_rs_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pts, n, axis, k0, v0);
-    hipError_t e = radix_sort(n, 8, k0, k1, v0, v1, hist, bsum, out, st);
+    hipError_t e = radix_sort(n, 8, k0, k1, v0, v1, hist, bsum, out, st, rank);
     if (e != hipSuccess || !coord) return e;
     // an even number of passes leaves the sorted keys in k0
     k_rs_decode<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(k0, out, pts, n, axis, coord);
@@ -413,17 +421,6 @@ struct pt_rec {
     double x, y;
     int32_t idx, seg;
 };
-
-// Inverse permutations of the two presorts: rank of every original index.
-__global__ void k_rank_inv(const int32_t *__restrict__ px, const int32_t *__restrict__ py, int64_t n,
-                           int32_t *__restrict__ rxo, int32_t *__restrict__ ryo)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        rxo[min(max((int64_t)px[i], (int64_t)0), n - 1)] = (int32_t)i;
-        ryo[min(max((int64_t)py[i], (int64_t)0), n - 1)] = (int32_t)i;
-    }
-}
 
 __global__ void k_srec_init(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
                             const int32_t *__restrict__ rxo, const int32_t *__restrict__ ryo, int64_t n,
@@ -1434,15 +1431,14 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         int32_t *vy0 = reinterpret_cast<int32_t *>(ky1 + ns), *vy1 = vy0 + ns;
         CK(hipEventRecord(a.ev_fork, st));
         CK(hipStreamWaitEvent(a.side, a.ev_fork, 0));
-        CK(presort(a.src, ns, 1, ky0, ky1, vy0, vy1, WS(int32_t, lay.hist2), bsum, py, ys, a.side));
-        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st));
+        CK(presort(a.src, ns, 1, ky0, ky1, vy0, vy1, WS(int32_t, lay.hist2), bsum, py, ys, a.side, ryo));
+        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st, rxo));
         CK(hipEventRecord(a.ev_join, a.side));
         CK(hipStreamWaitEvent(st, a.ev_join, 0));
     } else {
-        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st));
-        CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, st));
+        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st, rxo));
+        CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, st, ryo));
     }
-    k_rank_inv<<<nblk256(ns), 256, 0, st>>>(px, py, ns, rxo, ryo);
     k_srec_init<<<nblk256(ns), 256, 0, st>>>(px, py, rxo, ryo, ns, xb[0], yb[0]);
     k_fill_u8<<<nblk256(2 * bstride), 256, 0, st>>>(bxc, 2 * bstride); // the root: both lists in buffer 0
     if (nt) {
