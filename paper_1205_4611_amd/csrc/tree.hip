@@ -251,7 +251,10 @@ __global__ void __launch_bounds__(1024) k_rs_offsets(const int32_t *__restrict__
 // every element its place in the block's digit-ordered tile, staged in LDS and
 // written out so that consecutive threads write consecutive addresses of a
 // digit's run.  Stable: the block's order is wave-major, then in order.
-__global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict__ kin,
+// Keys and values are staged one after the other through the same buffer,
+// with the digit of every staged slot kept, so that the LDS use (39.9 KB) lets
+// 4 blocks share a CU and a 4M-key pass runs in one round of blocks.
+__global__ void __launch_bounds__(RS_T, 4) k_rs_scatter(const uint64_t *__restrict__ kin,
                                                       const int32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout,
                                                       int32_t *__restrict__ vout, int64_t n,
@@ -259,11 +262,13 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
                                                       int nblk, int32_t *__restrict__ rank)
 {
     constexpr int NW = RS_T / WAVE, PER_W = RS_BLOCK / NW, IT = PER_W / WAVE;
-    __shared__ uint64_t sk[RS_BLOCK];
-    __shared__ int32_t sv[RS_BLOCK];
-    __shared__ int32_t wc[NW][256]; // per-wave digit counts, then per-wave digit bases
-    __shared__ int32_t dstart[256];
+    static_assert(PER_W <= 65535 && RS_BLOCK <= 65535, "per-wave counts and bases are 16-bit");
+    __shared__ uint64_t sk[RS_BLOCK];   // staged keys, then (as int32) staged values
+    __shared__ uint8_t sd[RS_BLOCK];    // digit of every staged slot
+    __shared__ uint16_t wc[NW][256];    // per-wave digit counts, then per-wave digit bases
+    __shared__ int32_t dstart[256];     // digit starts in the tile, then output base - start
     __shared__ int32_t sh[NW];
+    int32_t *sv = reinterpret_cast<int32_t *>(sk);
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
 #pragma unroll
     for (int q = 0; q < NW; ++q) wc[q][tid] = 0;
@@ -293,7 +298,7 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
         }
         const int32_t c = wc[w][d];
         rk[t] = valid ? c + __popcll(peers & lt) : -1;
-        if (valid && __popcll(peers & lt) == 0) wc[w][d] = c + __popcll(peers);
+        if (valid && __popcll(peers & lt) == 0) wc[w][d] = (uint16_t)(c + __popcll(peers));
     }
     __syncthreads();
     {
@@ -302,30 +307,43 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t *__restrict_
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
             const int32_t v = wc[q][tid];
-            wc[q][tid] = s;
+            wc[q][tid] = (uint16_t)s;
             s += v;
         }
         int32_t tot;
         dstart[tid] = block_excl_scan(s, sh, &tot);
     }
     __syncthreads();
+    // rk[t] becomes the element's slot in the tile (-1: none)
 #pragma unroll
     for (int t = 0; t < IT; ++t) {
         if (rk[t] >= 0) {
             const int d = (int)((key[t] >> shift) & 255);
-            const int p = min(dstart[d] + wc[w][d] + rk[t], RS_BLOCK - 1);
+            const int p = min(dstart[d] + (int)wc[w][d] + rk[t], RS_BLOCK - 1);
+            rk[t] = p;
             sk[p] = key[t];
-            sv[p] = val[t];
+            sd[p] = (uint8_t)d;
         }
     }
     __syncthreads();
+    // output base of every digit less its start in the tile: slot j of digit d
+    // goes to position dstart[d] + j
+    dstart[tid] = off[(int64_t)tid * nblk + blockIdx.x] - dstart[tid];
+    __syncthreads();
     const int nvalid = (int)min((int64_t)RS_BLOCK, n - base);
     for (int j = tid; j < nvalid; j += RS_T) {
-        const uint64_t kk = sk[j];
-        const int d = (int)((kk >> shift) & 255);
-        int64_t pos = (int64_t)off[(int64_t)d * nblk + blockIdx.x] + (j - dstart[d]);
+        int64_t pos = (int64_t)dstart[sd[j]] + j;
         pos = pos < 0 ? 0 : (pos >= n ? n - 1 : pos); // never leave the array
-        kout[pos] = kk;
+        kout[pos] = sk[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < IT; ++t)
+        if (rk[t] >= 0) sv[rk[t]] = val[t];
+    __syncthreads();
+    for (int j = tid; j < nvalid; j += RS_T) {
+        int64_t pos = (int64_t)dstart[sd[j]] + j;
+        pos = pos < 0 ? 0 : (pos >= n ? n - 1 : pos);
         const int32_t v = sv[j];
         vout[pos] = v;
         // last pass of a presort: the values are the original indices, and
