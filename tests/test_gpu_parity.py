@@ -87,6 +87,15 @@ def _case(name):
     if name == "lattice_ties":
         g = _lattice()
         return g, np.concatenate([g[::7], workloads.points("uniform", 40, 74)]), 2
+    if name in ("dense_core", "dense_core_L6"):
+        # a tight core inside sparse uniform points: the boxes next to the core
+        # have hundreds of strong boxes, so their children's candidate sets
+        # (above 512) are shared by a workgroup in the list build
+        n, frac, sig, L = (40_000, 0.9, 1e-3, 5) if name == "dense_core" else (60_000, 0.95, 3e-4, 6)
+        rng = np.random.default_rng(97)
+        nc = int(n * frac)
+        core = (0.37 + 0.41j) + sig * (rng.standard_normal(nc) + 1j * rng.standard_normal(nc))
+        return np.concatenate([core, rng.random(n - nc) + 1j * rng.random(n - nc)]), None, L
     if name == "signed_zeros":
         # -0 and +0 compare equal (ties broken by index) but the sign of a
         # zero box end reaches the centre: most zero coordinates are -0
@@ -123,7 +132,8 @@ def _compare_topology(orc, top, T, L):
 
 
 @pytest.mark.parametrize("swap", [False, True])
-@pytest.mark.parametrize("name", [c[0] for c in TREE_CASES] + ["lattice_ties", "signed_zeros"])
+@pytest.mark.parametrize("name", [c[0] for c in TREE_CASES] + ["lattice_ties", "signed_zeros", "dense_core",
+                                                               "dense_core_L6"])
 def test_tree_and_lists_bitexact(fmm, orc, name, swap):
     src, tgt, L = _case(name)
     m = workloads.strengths(len(src), 75)
@@ -132,6 +142,9 @@ def test_tree_and_lists_bitexact(fmm, orc, name, swap):
     T = orc.Tree(src, L, tgt=tgt, swap=swap)
     if swap and name == "clusters20k":
         assert len(T.m2p[1]) > 0, "case does not exercise the swapped criterion"
+    if name.startswith("dense_core"):
+        # some box has more than 512 candidates (4 x its parent's strong count)
+        assert max(4 * int(np.diff(T.strong[l][0]).max()) for l in range(L)) > 512
     _compare_topology(orc, top, T, L)
 
 
@@ -140,7 +153,8 @@ def test_tree_and_lists_bitexact(fmm, orc, name, swap):
 @pytest.mark.parametrize("name,p,swap", [("uniform10k", 17, False), ("clusters20k", 12, False),
                                          ("gauss10_targets", 20, False), ("lattice_ties", 30, False),
                                          ("spiral_ragged", 9, False), ("clusters20k", 17, True),
-                                         ("gauss10_targets", 14, True), ("spiral_ragged", 21, True)])
+                                         ("gauss10_targets", 14, True), ("spiral_ragged", 21, True),
+                                         ("dense_core", 12, True)])
 def test_fmm_matches_oracle_fmm(fmm, orc, name, p, swap, kernel):
     src, tgt, L = _case(name)
     m = workloads.strengths(len(src), 76)
