@@ -1383,12 +1383,12 @@ __global__ void k_gather(const double *__restrict__ src, const double *__restric
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ns) {
-        int64_t j = perm[i];
+        const int64_t j = min(max((int64_t)perm[i], (int64_t)0), ns - 1);
         srcs[i] = make_double4(src[2 * j], src[2 * j + 1], m[2 * j], m[2 * j + 1]);
         if (m32) m32[i] = make_float2((float)m[2 * j], (float)m[2 * j + 1]);
     }
     if (i < nt) {
-        int64_t j = tperm[i];
+        const int64_t j = min(max((int64_t)tperm[i], (int64_t)0), nt - 1);
         tgts[i] = make_double2(tgt[2 * j], tgt[2 * j + 1]);
     }
 }
