@@ -152,19 +152,33 @@ __device__ __forceinline__ bool box_setup(const double *centre, const double *ra
     return true;
 }
 
+// The MLP of one pair.  w must be 16-byte aligned: the rows of W1 and the
+// blocks of b1 and W2 are read as float4 (half the LDS instructions of
+// one-float reads); the operations and their order are those of the loop
+// over hidden units j and inputs i.
 __device__ __forceinline__ float mlp_eval(const float *__restrict__ w, const float f[FMM2D_PORDER_NFEAT])
 {
+    static_assert(FMM_NF == 8 && FMM_HID % 4 == 0, "float4 reads of the weights");
     const float *W1 = w, *b1 = W1 + FMM_HID * FMM_NF, *W2 = b1 + FMM_HID, *b2 = W2 + FMM_HID;
     const float *mu = b2 + 1, *isd = mu + FMM_NF;
     float x[FMM_NF];
 #pragma unroll
     for (int i = 0; i < FMM_NF; ++i) x[i] = (f[i] - mu[i]) * isd[i];
     float y = b2[0];
-    for (int j = 0; j < FMM_HID; ++j) {
-        float z = b1[j];
+    for (int j0 = 0; j0 < FMM_HID; j0 += 4) {
+        const float4 bb = *reinterpret_cast<const float4 *>(b1 + j0);
+        const float4 ww = *reinterpret_cast<const float4 *>(W2 + j0);
+        const float bj[4] = {bb.x, bb.y, bb.z, bb.w}, w2[4] = {ww.x, ww.y, ww.z, ww.w};
 #pragma unroll
-        for (int i = 0; i < FMM_NF; ++i) z = fmaf(W1[j * FMM_NF + i], x[i], z);
-        y = fmaf(W2[j], fmaxf(z, 0.0f), y);
+        for (int u = 0; u < 4; ++u) {
+            const float4 a0 = *reinterpret_cast<const float4 *>(W1 + (j0 + u) * FMM_NF);
+            const float4 a1 = *reinterpret_cast<const float4 *>(W1 + (j0 + u) * FMM_NF + 4);
+            const float wr[FMM_NF] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            float z = bj[u];
+#pragma unroll
+            for (int i = 0; i < FMM_NF; ++i) z = fmaf(wr[i], x[i], z);
+            y = fmaf(w2[u], fmaxf(z, 0.0f), y);
+        }
     }
     return y;
 }
@@ -267,7 +281,7 @@ __device__ __forceinline__ int order_class(int q)
 // whole weak list, is computed once per unit.
 __global__ void __launch_bounds__(256) k_porder(fmm_porder_args a, const float *__restrict__ model)
 {
-    __shared__ float smodel[FMM2D_PORDER_MODEL_FLOATS];
+    __shared__ __align__(16) float smodel[FMM2D_PORDER_MODEL_FLOATS];
     // per wave: the unit's sources and orders (lane i keeps entries i, i + 64, ...)
     __shared__ int32_t s_src[256 / WAVE][PORDER_RCH * WAVE];
     __shared__ uint8_t s_q[256 / WAVE][PORDER_RCH * WAVE];
@@ -502,7 +516,7 @@ __global__ void k_budget(const double *__restrict__ vmin, const int32_t *__restr
 __global__ void __launch_bounds__(MLP_BLOCK) k_mlp_forward(const float *__restrict__ w, const float *__restrict__ x,
                                                            int64_t n, float *__restrict__ y)
 {
-    __shared__ float sw[FMM2D_PORDER_MODEL_FLOATS];
+    __shared__ __align__(16) float sw[FMM2D_PORDER_MODEL_FLOATS];
     for (int k = threadIdx.x; k < FMM2D_PORDER_MODEL_FLOATS; k += blockDim.x) sw[k] = w[k];
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
