@@ -156,7 +156,8 @@ hipError_t fmm_m2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_l2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_p2l(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_near_plan(const fmm_eval_args &a, hipStream_t st);
-// part 0: the near-field kernel; part 1: the reduction of heavy leaves' unit partials
+// part 0: the near-field kernel (part 2 then part 3: its heavy-leaf units,
+// then its light leaves, as two launches); part 1: the output kernel
 hipError_t fmm_p2p_l2p(const fmm_eval_args &a, double *phi, double *dphi, int part, hipStream_t st);
 
 // learned / given per-pair orders (porder.hip)

@@ -15,9 +15,10 @@ struct fmm2d_handle {
     double *d_binom;        // [FMM_BN][FMM_BN]
     hipEvent_t ev[FMM2D_NPHASE + 1];
     // side stream and its fork / join events: y presort (0, 1), tree done (2),
-    // M2L done (3), lists and plans done (4), far field done (5)
+    // M2L done (3), lists and plans done (4), far field done (5), leaf
+    // multipoles done (6)
     hipStream_t side;
-    hipEvent_t sev[6];
+    hipEvent_t sev[7];
     int timing_valid;
     hipStream_t last_stream;
     // learned order model (device copy, owned) and caller-given orders (not owned)
@@ -216,7 +217,7 @@ extern "C" int fmm2d_create(fmm2d_handle **out, int device)
     }
     for (int i = 0; i <= FMM2D_NPHASE && e == hipSuccess; ++i) e = hipEventCreate(&h->ev[i]);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
-    for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&h->sev[i], hipEventDisableTiming);
+    for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&h->sev[i], hipEventDisableTiming);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) {
         fmm2d_destroy(h);
@@ -234,7 +235,7 @@ extern "C" void fmm2d_destroy(fmm2d_handle *h)
     (void)hipSetDevice(h->device);
     for (int i = 0; i <= FMM2D_NPHASE; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 7; ++i)
         if (h->sev[i]) (void)hipEventDestroy(h->sev[i]);
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->d_status) (void)hipFree(h->d_status);
@@ -389,6 +390,7 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     auto upward = [&]() -> int {
         HIPCHK(h, fmm_p2m(ea, sb));
         if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2M], sb));
+        if (fork) HIPCHK(h, hipEventRecord(h->sev[6], sb));
         HIPCHK(h, fmm_m2m(ea, sb));
         if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_M2M], sb));
         if (use_model)
@@ -425,17 +427,21 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
         HIPCHK(h, hipStreamWaitEvent(sb, h->sev[4], 0));
         if ((rc2 = downward())) return rc2;
         HIPCHK(h, hipEventRecord(h->sev[5], sb));
-        // The near kernel needs only the leaf multipoles (M2P), but it starts
-        // after M2L: M2L waves hold 160 VGPRs and find little room once the
-        // near kernel's 48-VGPR waves fill the CUs, so side by side M2L ran
-        // past the end of the near kernel; alone it runs at full rate, and
-        // L2L and P2L run beside the near kernel.
+        // The near field needs only the lists and the leaf multipoles (M2P).
+        // Its heavy-leaf units run beside the order phase; its light leaves
+        // wait for M2L: M2L waves hold 160 VGPRs and find little room once
+        // the near kernel's 48-VGPR waves fill the CUs, so side by side M2L
+        // ran past the end of the near kernel; alone it runs at full rate,
+        // and L2L and P2L run beside the light leaves.
+        HIPCHK(h, hipStreamWaitEvent(st, h->sev[6], 0));
+        HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 2, st));
         HIPCHK(h, hipStreamWaitEvent(st, h->sev[3], 0));
+        HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 3, st));
     } else {
         if ((rc2 = upward())) return rc2;
         if ((rc2 = downward())) return rc2;
+        HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 0, st));
     }
-    HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 0, st));
     if (timing) HIPCHK(h, hipEventRecord(h->ev[1 + FMM2D_PH_P2P], st));
     if (fork) HIPCHK(h, hipStreamWaitEvent(st, h->sev[5], 0)); // L2P reads the local expansions
     HIPCHK(h, fmm_p2p_l2p(ea, LOG ? phi : nullptr, dphi, 1, st));
