@@ -767,7 +767,7 @@ struct ps_list {
     src_rec *buf0, *buf1;        // the list's two buffers
     const uint8_t *bit;          // per segment: the buffer holding this list
     const int32_t *LO;           // exclusive prefix of the moving lo counts
-    int32_t *tcnt;               // per tile: moving lo records (COUNT), then their exclusive prefix
+    int32_t *tcnt;               // per tile: moving lo records (written by the count pass)
 };
 struct ps_batch {
     ps_list l[2];
@@ -791,8 +791,18 @@ __global__ void __launch_bounds__(LB_T) k_part_src(ps_batch pb)
     // of their split (pivot rank, axis, buffer bit) and placement (LO, nlo)
     __shared__ int32_t win[LB_SEGW], wpi[LB_SEGW], wlo[LB_SEGW], wnl[LB_SEGW];
     __shared__ uint8_t wax[LB_SEGW], wbit[LB_SEGW];
+    __shared__ int32_t wpre[LB_T / WAVE];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int32_t tile = blockIdx.x;
+    if (!COUNT) {
+        // moving lo records of the tiles before this one: the sum of their
+        // counts (read from L2, reduced while the records load)
+        int32_t part = 0;
+        for (int32_t k = tid; k < tile; k += LB_T) part += p.tcnt[k];
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, WAVE);
+        if (lane == 0) wpre[w] = part;
+    }
     const int64_t tb = (int64_t)tile * LB_B, te = min(tb + LB_B, pb.n);
     const int32_t j0 = min(max(pb.tseg[tile], 0), pb.nseg - 1);
     {
@@ -876,7 +886,9 @@ __global__ void __launch_bounds__(LB_T) k_part_src(ps_batch pb)
         wc[lane] = inc - v;
     }
     __syncthreads();
-    const int32_t carry = p.tcnt[tile]; // moving lo records of the tiles before
+    int32_t carry = 0; // moving lo records of the tiles before
+#pragma unroll
+    for (int q2 = 0; q2 < LB_T / WAVE; ++q2) carry += wpre[q2];
 #pragma unroll
     for (int i = 0; i < LB_I; ++i) {
         if (sg[i] < 0) continue;
@@ -891,22 +903,6 @@ __global__ void __launch_bounds__(LB_T) k_part_src(ps_batch pb)
         int64_t dst = lo ? (int64_t)st + rank : (int64_t)st + nlj + (pos - st - rank);
         dst = dst < 0 ? 0 : (dst >= pb.n ? pb.n - 1 : dst); // never leave the array
         ((bj & 1) ? p.buf0 : p.buf1)[dst] = r[i];
-    }
-}
-
-// Exclusive scan of the tile counts of both source lists (block q: list q).
-__global__ void __launch_bounds__(1024) k_tile_scan(ps_batch pb)
-{
-    __shared__ int32_t sh[1024 / WAVE];
-    int32_t *c = pb.l[blockIdx.x].tcnt;
-    int32_t carry = 0;
-    for (int32_t c0 = 0; c0 < pb.ntiles; c0 += blockDim.x) {
-        const int32_t k = c0 + threadIdx.x;
-        const int32_t v = k < pb.ntiles ? c[k] : 0;
-        int32_t t;
-        const int32_t ex = block_excl_scan(v, sh, &t);
-        if (k < pb.ntiles) c[k] = carry + ex;
-        carry += t;
     }
 }
 
@@ -1566,7 +1562,6 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
             pb.ntiles = st_tiles;
             pb.status = a.status;
             k_part_src<true><<<dim3((unsigned)st_tiles, 2), LB_T, 0, st>>>(pb);
-            k_tile_scan<<<2, 1024, 0, st>>>(pb);
             k_part_src<false><<<dim3((unsigned)st_tiles, 2), LB_T, 0, st>>>(pb);
             CK(hipGetLastError());
         }
