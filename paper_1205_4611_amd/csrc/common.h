@@ -200,7 +200,18 @@ hipError_t fmm_direct(int64_t ns, const double *src, const double *m, int64_t nt
                       double *phi, double *dphi, hipStream_t st);
 
 // device-wide exclusive scan of int32 (n entries) into out[0..n]; out[n] is
-// the total; base (device, may be NULL) is added to every entry.
+// the total; base (device, may be NULL) is added to every entry; blocksums
+// holds fmm_scan_blocks(n) + 1 entries.
 hipError_t fmm_scan_i32(const int32_t *in, int32_t *out, int64_t n, const int32_t *base,
                         int32_t *blocksums, hipStream_t st);
+// up to FMM_SCAN_JOBS such scans of arrays of the same length, in one set of
+// launches (each job with its own block sums)
+#define FMM_SCAN_JOBS 4
+struct fmm_scan_jobs {
+    const int32_t *in[FMM_SCAN_JOBS];
+    int32_t *out[FMM_SCAN_JOBS];
+    const int32_t *base[FMM_SCAN_JOBS];
+    int32_t *bs[FMM_SCAN_JOBS];
+};
+hipError_t fmm_scan_i32_jobs(const fmm_scan_jobs &J, int njobs, int64_t n, hipStream_t st);
 __host__ __device__ int64_t fmm_scan_blocks(int64_t n);

@@ -106,7 +106,7 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->keys[1] = take(8 * nmax);
     lay->vals[0] = take(4 * nmax);
     lay->vals[1] = take(4 * nmax);
-    lay->hist = take(4 * (hist_n > seg_scan_n ? hist_n : seg_scan_n));
+    lay->hist = take(4 * (hist_n > 3 * seg_scan_n ? hist_n : 3 * seg_scan_n)); // also 3 block-sum arrays
     lay->hist2 = take(4 * hist_n);
     {
         int64_t a = fmm_scan_blocks(hist_n) + 1;
@@ -153,7 +153,7 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->poff = take(4 * (lay->nleaf + 1));
     lay->midx = take(4 * lay->leafcap);
     lay->pidx = take(4 * lay->leafcap);
-    lay->lbsum = take(4 * (fmm_scan_blocks(lay->nleaf) + 2));
+    lay->lbsum = take(4 * FMM_SCAN_JOBS * (fmm_scan_blocks(lay->nleaf) + 2));
     lay->lhvy = take(4 * lay->nb);
     lay->lhcnt = take(4 * (L + 2));
     lay->srcs = take(32 * ns);

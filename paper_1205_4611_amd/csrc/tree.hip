@@ -18,6 +18,8 @@
 //    k becomes segments 2j, 2j+1 of step k+1 and no host round-trip is needed.
 #pragma clang fp contract(off)
 
+#include <string.h>
+
 #include "common.h"
 
 #define WAVE 64
@@ -59,10 +61,12 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *sh, int32
     return off + inc - v;
 }
 
-__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t *__restrict__ in, int64_t n,
-                                                         int32_t *__restrict__ bs)
+// Up to 4 exclusive scans of arrays of the same length in one set of launches
+// (grid row y: job y); job y's block sums live in bs[y].
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(fmm_scan_jobs J, int64_t n)
 {
     __shared__ int32_t sh[SCAN_T / WAVE];
+    const int32_t *__restrict__ in = J.in[blockIdx.y];
     const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
     int32_t s = 0;
 #pragma unroll
@@ -70,17 +74,16 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t *__restric
         if (base + i < n) s += in[base + i];
     int32_t tot;
     block_excl_scan(s, sh, &tot);
-    if (threadIdx.x == 0) bs[blockIdx.x] = tot;
+    if (threadIdx.x == 0) J.bs[blockIdx.y][blockIdx.x] = tot;
 }
 
-// Single block: exclusive scan of the block sums in place (+ *base), writes
-// the grand total to bs[nb] and, if out_total, to *out_total.
-__global__ void __launch_bounds__(1024) k_scan_sums(int32_t *__restrict__ bs, int64_t nb,
-                                                     const int32_t *__restrict__ base,
-                                                     int32_t *__restrict__ out_total)
+// One block per job: exclusive scan of the block sums in place (+ *base),
+// the grand total to bs[nb] and to out[n].
+__global__ void __launch_bounds__(1024) k_scan_sums(fmm_scan_jobs J, int64_t nb, int64_t n)
 {
     __shared__ int32_t sh[1024 / WAVE];
-    int32_t carry = base ? *base : 0;
+    int32_t *__restrict__ bs = J.bs[blockIdx.y];
+    int32_t carry = J.base[blockIdx.y] ? *J.base[blockIdx.y] : 0;
     for (int64_t c = 0; c < nb; c += blockDim.x) {
         int64_t k = c + threadIdx.x;
         int32_t v = k < nb ? bs[k] : 0;
@@ -91,15 +94,15 @@ __global__ void __launch_bounds__(1024) k_scan_sums(int32_t *__restrict__ bs, in
     }
     if (threadIdx.x == 0) {
         bs[nb] = carry;
-        if (out_total) *out_total = carry;
+        J.out[blockIdx.y][n] = carry;
     }
 }
 
-__global__ void __launch_bounds__(SCAN_T) k_scan_down(const int32_t *__restrict__ in,
-                                                       int32_t *__restrict__ out, int64_t n,
-                                                       const int32_t *__restrict__ bs)
+__global__ void __launch_bounds__(SCAN_T) k_scan_down(fmm_scan_jobs J, int64_t n)
 {
     __shared__ int32_t sh[SCAN_T / WAVE];
+    const int32_t *__restrict__ in = J.in[blockIdx.y];
+    int32_t *__restrict__ out = J.out[blockIdx.y];
     const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I;
     int32_t v[SCAN_I];
     int32_t s = 0;
@@ -109,7 +112,7 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_down(const int32_t *__restrict_
         s += v[i];
     }
     int32_t tot;
-    int32_t run = block_excl_scan(s, sh, &tot) + bs[blockIdx.x];
+    int32_t run = block_excl_scan(s, sh, &tot) + J.bs[blockIdx.y][blockIdx.x];
 #pragma unroll
     for (int i = 0; i < SCAN_I; ++i) {
         if (base + i < n) out[base + i] = run;
@@ -117,12 +120,13 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_down(const int32_t *__restrict_
     }
 }
 
-// Small arrays: one block of 1024 threads walks the array in chunks.
-__global__ void __launch_bounds__(1024) k_scan_single(const int32_t *__restrict__ in, int32_t *__restrict__ out,
-                                                       int64_t n, const int32_t *__restrict__ base)
+// Small arrays: one block of 1024 threads per job walks the array in chunks.
+__global__ void __launch_bounds__(1024) k_scan_single(fmm_scan_jobs J, int64_t n)
 {
     __shared__ int32_t sh[1024 / WAVE];
-    int32_t carry = base ? *base : 0;
+    const int32_t *__restrict__ in = J.in[blockIdx.y];
+    int32_t *__restrict__ out = J.out[blockIdx.y];
+    int32_t carry = J.base[blockIdx.y] ? *J.base[blockIdx.y] : 0;
     for (int64_t c = 0; c < n; c += blockDim.x) {
         const int64_t k = c + threadIdx.x;
         const int32_t v = k < n ? in[k] : 0;
@@ -134,18 +138,30 @@ __global__ void __launch_bounds__(1024) k_scan_single(const int32_t *__restrict_
     if (threadIdx.x == 0) out[n] = carry;
 }
 
+hipError_t fmm_scan_i32_jobs(const fmm_scan_jobs &J, int njobs, int64_t n, hipStream_t st)
+{
+    if (njobs < 1 || njobs > FMM_SCAN_JOBS) return hipErrorInvalidValue;
+    if (n <= 16384) {
+        k_scan_single<<<dim3(1, njobs), 1024, 0, st>>>(J, n);
+        return hipGetLastError();
+    }
+    const int64_t nb = fmm_scan_blocks(n);
+    k_scan_reduce<<<dim3((unsigned)nb, njobs), SCAN_T, 0, st>>>(J, n);
+    k_scan_sums<<<dim3(1, njobs), 1024, 0, st>>>(J, nb, n);
+    k_scan_down<<<dim3((unsigned)nb, njobs), SCAN_T, 0, st>>>(J, n);
+    return hipGetLastError();
+}
+
 hipError_t fmm_scan_i32(const int32_t *in, int32_t *out, int64_t n, const int32_t *base,
                         int32_t *blocksums, hipStream_t st)
 {
-    if (n <= 16384) {
-        k_scan_single<<<1, 1024, 0, st>>>(in, out, n, base);
-        return hipGetLastError();
-    }
-    int64_t nb = fmm_scan_blocks(n);
-    if (nb > 0) k_scan_reduce<<<(unsigned)nb, SCAN_T, 0, st>>>(in, n, blocksums);
-    k_scan_sums<<<1, 1024, 0, st>>>(blocksums, nb, base, out + n);
-    if (nb > 0) k_scan_down<<<(unsigned)nb, SCAN_T, 0, st>>>(in, out, n, blocksums);
-    return hipGetLastError();
+    fmm_scan_jobs J;
+    memset(&J, 0, sizeof(J));
+    J.in[0] = in;
+    J.out[0] = out;
+    J.base[0] = base;
+    J.bs[0] = blocksums;
+    return fmm_scan_i32_jobs(J, 1, n, st);
 }
 
 // ------------------------------------------------------- radix presort --
@@ -1538,9 +1554,13 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         // exclusive scans of the lo counts of the moving source lists (and the
         // targets' lo counts) over segments
         if (!fuse) {
-            CK(fmm_scan_i32(nlox, LO, nseg, nullptr, hist, st));
-            CK(fmm_scan_i32(nloy, LOY, nseg, nullptr, hist, st));
-            if (nt) CK(fmm_scan_i32(tlo, TLO, nseg, nullptr, hist, st));
+            fmm_scan_jobs J;
+            memset(&J, 0, sizeof(J));
+            const int64_t bstr = fmm_scan_blocks(nseg) + 1;
+            J.in[0] = nlox; J.out[0] = LO; J.bs[0] = hist;
+            J.in[1] = nloy; J.out[1] = LOY; J.bs[1] = hist + bstr;
+            J.in[2] = tlo; J.out[2] = TLO; J.bs[2] = hist + 2 * bstr;
+            CK(fmm_scan_i32_jobs(J, nt ? 3 : 2, nseg, st));
         }
         {
             ps_batch pb;
@@ -1656,13 +1676,17 @@ hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st)
         // LIST_HB workgroups for the heavy boxes, then 4 light boxes per workgroup
         const unsigned nwb = (unsigned)(LIST_HB + (nbox(l) + 3) / 4);
         k_lists<false><<<nwb, 256, 0, st>>>(la);
-        CK(fmm_scan_i32(wcnt, woff + start_off(l), nbox(l), woff + start_off(l - 1) + nbox(l - 1),
-                        lbsum, st));
-        CK(fmm_scan_i32(scnt, soff + start_off(l), nbox(l), soff + start_off(l - 1) + nbox(l - 1),
-                        lbsum, st));
-        if (la.swap) {
-            CK(fmm_scan_i32(la.mcnt, WS(int32_t, lay.moff), nbox(l), nullptr, lbsum, st));
-            CK(fmm_scan_i32(la.pcnt, WS(int32_t, lay.poff), nbox(l), nullptr, lbsum, st));
+        {
+            // weak and strong offsets (and at the finest level M2P and P2L) in one set of launches
+            fmm_scan_jobs J;
+            memset(&J, 0, sizeof(J));
+            const int64_t bstr = fmm_scan_blocks(nbox(l)) + 1;
+            J.in[0] = wcnt; J.out[0] = woff + start_off(l); J.base[0] = woff + start_off(l - 1) + nbox(l - 1);
+            J.in[1] = scnt; J.out[1] = soff + start_off(l); J.base[1] = soff + start_off(l - 1) + nbox(l - 1);
+            J.in[2] = la.mcnt; J.out[2] = WS(int32_t, lay.moff);
+            J.in[3] = la.pcnt; J.out[3] = WS(int32_t, lay.poff);
+            for (int q = 0; q < 4; ++q) J.bs[q] = lbsum + q * bstr;
+            CK(fmm_scan_i32_jobs(J, la.swap ? 4 : 2, nbox(l), st));
         }
         k_lists<true><<<nwb, 256, 0, st>>>(la);
         CK(hipGetLastError());
