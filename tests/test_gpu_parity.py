@@ -69,6 +69,10 @@ TREE_CASES = [
     # deep levels with separate targets: every split runs as a global step and
     # the last ones cut tiles into hundreds of segments of a few sources
     ("dense_L5_targets", "uniform", 5_000, 5, ("uniform", 300, 75)),
+    # separate targets at L = 6: the last split steps have more than 1024
+    # segments, so the lo counts of both source lists and of the targets are
+    # scanned in one batched set of launches
+    ("clusters_L6_targets", "clusters", 20_000, 6, ("uniform", 3_000, 76)),
 ]
 
 
