@@ -160,7 +160,7 @@ def main():
                     help="only run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the multi-GPU path is not part of this build "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
