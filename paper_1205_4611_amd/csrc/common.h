@@ -92,6 +92,7 @@ struct fmm_layout {
     int64_t leafcap;             // entries of each M2P / P2L array
     size_t lbsum;                // list scan block sums
     size_t lhvy, lhcnt;          // list build: heavy boxes per level (level-local ids), their counts
+    size_t lhpart;               // list build: class counts per heavy box and part (16 parts)
     size_t srcs;                 // double4 sources in leaf order
     size_t tgts;                 // double2 targets in leaf order
     size_t m32;                  // float2 strengths in leaf order (mixed)

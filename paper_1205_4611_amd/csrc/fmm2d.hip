@@ -156,6 +156,7 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->lbsum = take(4 * FMM_SCAN_JOBS * (fmm_scan_blocks(lay->nleaf) + 2));
     lay->lhvy = take(4 * lay->nb);
     lay->lhcnt = take(4 * (L + 2));
+    lay->lhpart = take(4 * 4 * 16 * lay->nleaf); // heavy boxes of a level <= 4^L, 16 parts, 4 counts
     lay->srcs = take(32 * ns);
     lay->tgts = take(16 * nt);
     lay->m32 = mixed == 1 ? take(8 * ns) : 0;

@@ -1190,6 +1190,7 @@ struct list_args {
     int32_t lcap;                  // capacity of the M2P / P2L arrays
     const int32_t *hvy, *hcnt;     // heavy boxes of this level (level-local ids) and their count
     int32_t *hvy_next, *hcnt_next; // the same for the next level (fill pass appends), or NULL
+    int32_t *hpart;                // per heavy box and part: its 4 class counts (count pass)
 };
 
 // A box whose candidate set (4 x its parent's strong count) exceeds
@@ -1200,6 +1201,7 @@ struct list_args {
 // one wave walking its children's candidates would set the launch's length.
 #define LIST_HEAVY 512
 #define LIST_HB 256
+#define LIST_KP 16 // parts (of 4 waves) a heavy box is split into
 
 struct list_cnt {
     int32_t w, s, m, p; // weak, strong, M2P, P2L
@@ -1286,7 +1288,15 @@ __device__ __forceinline__ void list_next_heavy(const list_args &a, int32_t b, i
 {
     if (a.hvy_next && 4 * nstrong > LIST_HEAVY) {
         const int32_t pos = atomicAdd(a.hcnt_next, 4);
-        for (int i = 0; i < 4; ++i) a.hvy_next[pos + i] = 4 * b + i;
+        for (int i = 0; i < 4; ++i) {
+            const int32_t c = 4 * b + i;
+            a.hvy_next[pos + i] = c;
+            // the next level's count pass adds the parts' counts to these
+            a.wcnt[c] = 0;
+            a.scnt[c] = 0;
+            a.mcnt[c] = 0;
+            a.pcnt[c] = 0;
+        }
     }
 }
 
@@ -1325,46 +1335,56 @@ __global__ void __launch_bounds__(256) k_lists(list_args a)
         }
         return;
     }
-    // heavy boxes: the 4 waves take contiguous ranges of 64-candidate chunks
+    // heavy boxes: LIST_KP parts of 4 waves each; wave slot v = 4 part + wave
+    // takes a contiguous range of 64-candidate chunks
     __shared__ list_cnt hc[4];
     const int32_t nh = min(*a.hcnt, a.nbl);
-    for (int32_t h = blockIdx.x; h < nh; h += LIST_HB) {
+    for (int32_t it = blockIdx.x; it < nh * LIST_KP; it += LIST_HB) {
+        const int32_t h = it / LIST_KP, part = it % LIST_KP;
         const int32_t b = min(max(a.hvy[h], 0), a.nbl - 1);
         const int32_t q = b >> 2;
         const int32_t e0 = min(a.psoff[q], a.cap), e1 = min(a.psoff[q + 1], a.cap);
         const int32_t ncand = 4 * (e1 - e0);
-        const int32_t C = (ncand + 4 * WAVE - 1) / (4 * WAVE) * WAVE;
-        const int32_t kb = min(w * C, ncand), ke = min(kb + C, ncand);
+        const int32_t C = (ncand + 4 * LIST_KP * WAVE - 1) / (4 * LIST_KP * WAVE) * WAVE;
+        const int32_t v = 4 * part + w;
+        const int32_t kb = min(v * C, ncand), ke = min(kb + C, ncand);
         const double cbx = a.centre[2 * (int64_t)b], cby = a.centre[2 * (int64_t)b + 1];
         const double rb = a.radius[b];
+        int32_t *hp = a.hpart + ((int64_t)h * LIST_KP) * 4;
         const list_cnt n = list_range<false>(a, b, e0, kb, ke, cbx, cby, rb, zero);
         if (lane == 0) hc[w] = n;
         __syncthreads();
         if (!FILL) {
             if (threadIdx.x == 0) {
                 list_cnt t = zero;
-                for (int v = 0; v < 4; ++v) {
-                    t.w += hc[v].w; t.s += hc[v].s; t.m += hc[v].m; t.p += hc[v].p;
+                for (int u = 0; u < 4; ++u) {
+                    t.w += hc[u].w; t.s += hc[u].s; t.m += hc[u].m; t.p += hc[u].p;
                 }
-                a.wcnt[b] = t.w;
-                a.scnt[b] = t.s;
+                hp[4 * part] = t.w;
+                hp[4 * part + 1] = t.s;
+                hp[4 * part + 2] = t.m;
+                hp[4 * part + 3] = t.p;
+                // integer sums: exact in any order
+                if (t.w) atomicAdd(a.wcnt + b, t.w);
+                if (t.s) atomicAdd(a.scnt + b, t.s);
                 if (a.swap) {
-                    a.mcnt[b] = t.m;
-                    a.pcnt[b] = t.p;
+                    if (t.m) atomicAdd(a.mcnt + b, t.m);
+                    if (t.p) atomicAdd(a.pcnt + b, t.p);
                 }
             }
         } else {
             bool over;
             list_cnt o = list_starts(a, b, over);
-            int32_t ns = 0;
-            for (int v = 0; v < 4; ++v) {
-                if (v < w) {
-                    o.w += hc[v].w; o.s += hc[v].s; o.m += hc[v].m; o.p += hc[v].p;
-                }
-                ns += hc[v].s;
+            for (int k = 0; k < part; ++k) {
+                o.w += hp[4 * k]; o.s += hp[4 * k + 1]; o.m += hp[4 * k + 2]; o.p += hp[4 * k + 3];
             }
-            if (threadIdx.x == 0) {
+            for (int u = 0; u < w; ++u) {
+                o.w += hc[u].w; o.s += hc[u].s; o.m += hc[u].m; o.p += hc[u].p;
+            }
+            if (part == 0 && threadIdx.x == 0) {
                 if (over) atomicOr(a.status, FMM_ST_LIST_OVERFLOW);
+                int32_t ns = 0;
+                for (int k = 0; k < LIST_KP; ++k) ns += hp[4 * k + 1];
                 list_next_heavy(a, b, ns);
             }
             list_range<true>(a, b, e0, kb, ke, cbx, cby, rb, o);
@@ -1673,6 +1693,7 @@ hipError_t fmm_build_lists(const fmm_tree_args &a, hipStream_t st)
         la.hcnt = hcnt + l;
         la.hvy_next = l < L ? hvy + box_off(l + 1) : nullptr;
         la.hcnt_next = l < L ? hcnt + l + 1 : nullptr;
+        la.hpart = WS(int32_t, lay.lhpart);
         // LIST_HB workgroups for the heavy boxes, then 4 light boxes per workgroup
         const unsigned nwb = (unsigned)(LIST_HB + (nbox(l) + 3) / 4);
         k_lists<false><<<nwb, 256, 0, st>>>(la);
