@@ -719,6 +719,77 @@ def pin_features_invariants(orc):
     assert not np.allclose(np.abs(A2[1:, 3]) / np.abs(A[1:, 3]).clip(1e-300), 1.0)
 
 
+class _HandTree:
+    """Hand-set geometry and weak pairs in the interface porder.features
+    reads (L, radius, centre, weak_pairs())."""
+
+    def __init__(self, L, radius, centre, pairs):
+        self.L = L
+        self.radius = radius
+        self.centre = centre
+        self._pairs = pairs
+
+    def weak_pairs(self):
+        lv, tb, sb = (np.array(c, np.int64) for c in zip(*self._pairs))
+        return lv, tb, sb
+
+
+def pin_features_closed_form(orc):
+    """Every order feature against its closed form.  Geometry and weak pairs
+    are set by hand (one leaf of zero radius, so its coefficients are scaled
+    by the floor 2^-20 rho_root); the multipoles are geometric, a_k = c t^k,
+    so |a_k| / sigma^k = |c| r^k with r = |t| / sigma and the coefficient
+    norms are finite geometric sums:
+      n1   = |c| (1 - r^(K+1)) / (1 - r)                 (k = 0..K)
+      tail = |c| (r^(floor(K/2)+1) - r^(K+1)) / (1 - r)   (k > K/2)
+    f4 = log10(n1_S / n1_root), f5 = log10(tail_S / n1_S), f6 =
+    log10(n1_S / sum over weak(T) of n1), f7 = log10 |weak(T)|, f0..f3 the
+    ratios of radii and distance and l / L.  K = min(p, 20): p = 24 and an
+    odd K = 15 are both checked."""
+    from oracle import porder
+    rng = np.random.default_rng(31)
+    L = 2
+    nb = orc.box_offset(L + 1)
+    radius = rng.uniform(0.02, 0.3, nb)
+    radius[0] = 0.9
+    radius[orc.box_offset(2) + 6] = 0.0          # a leaf of coincident points
+    centre = rng.uniform(0, 1, nb) + 1j * rng.uniform(0, 1, nb)
+    pairs = [(1, 0, 3), (1, 3, 0), (1, 1, 2)]
+    # level 2: target boxes with 1, 2, 3 and 5 weak sources (zero-radius leaf among them)
+    for t, srcs in ((0, (9,)), (5, (6, 14)), (6, (0, 5, 12)), (11, (1, 2, 6, 7, 15))):
+        pairs += [(2, t, s) for s in srcs]
+    T = _HandTree(L, radius, centre, pairs)
+    sig = np.maximum(radius, radius[0] * 2.0 ** -20)
+    c = rng.uniform(0.5, 2.0, nb) * np.exp(2j * np.pi * rng.random(nb))
+    r = rng.uniform(0.15, 0.85, nb)
+    t = r * sig * np.exp(2j * np.pi * rng.random(nb))
+    for p in (24, 15):
+        K = min(p, porder.FEAT_K)
+        A = c[:, None] * t[:, None] ** np.arange(p + 1)[None, :]
+        n1 = np.abs(c) * (1 - r ** (K + 1)) / (1 - r)
+        tail = np.abs(c) * (r ** (K // 2 + 1) - r ** (K + 1)) / (1 - r)
+        F = porder.features(T, A, p)
+        lv, tb, sb = T.weak_pairs()
+        gT = np.array([orc.box_offset(int(l)) for l in lv]) + tb
+        gS = np.array([orc.box_offset(int(l)) for l in lv]) + sb
+        d = np.abs(centre[gT] - centre[gS])
+        den = {}
+        cnt = {}
+        for g_t, g_s in zip(gT, gS):
+            den[g_t] = den.get(g_t, 0.0) + n1[g_s]
+            cnt[g_t] = cnt.get(g_t, 0) + 1
+        ref = np.empty_like(F)
+        ref[:, 0] = radius[gS] / d
+        ref[:, 1] = radius[gT] / d
+        ref[:, 2] = (radius[gS] + radius[gT]) / d
+        ref[:, 3] = lv / L
+        ref[:, 4] = np.log10(n1[gS] / n1[0])
+        ref[:, 5] = np.log10(tail[gS] / n1[gS])
+        ref[:, 6] = np.log10(n1[gS] / np.array([den[g] for g in gT]))
+        ref[:, 7] = np.log10(np.array([cnt[g] for g in gT], np.float64))
+        assert np.allclose(F, ref, rtol=1e-12, atol=1e-12), (p, np.max(np.abs(F - ref), axis=0))
+
+
 def _mlp_problem(seed, n=200):
     from oracle import porder
     rng = np.random.default_rng(seed)
@@ -833,5 +904,5 @@ ALL_PINS = [pin_level_rule, pin_direct_roots_of_unity, pin_direct_bruteforce, pi
             pin_tree_invariants, pin_tree_targets_on_pivot, pin_lists, pin_fmm_L0_is_direct,
             pin_fmm_theta_small_is_direct, pin_fmm_converges, pin_fmm_lattice_ties, pin_p2l_near_field, pin_swap_lists, pin_fmm_swap_converges, pin_operating_point, pin_branch,
             pin_pair_err_point_source, pin_pair_err_bounds_error, pin_labels_budget, pin_orders_uniform,
-            pin_orders_per_pair, pin_features_invariants, pin_mlp_forward_by_hand, pin_mlp_gradient,
+            pin_orders_per_pair, pin_features_invariants, pin_features_closed_form, pin_mlp_forward_by_hand, pin_mlp_gradient,
             pin_pinball_quantile, pin_adam_first_step, pin_orders_decision]

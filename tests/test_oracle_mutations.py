@@ -65,6 +65,15 @@ PY_MUTATIONS = [
     ("order rounding", "q = np.clip(np.ceil(np.clip(yd, -1e6, 1e6)), QMIN, p)", "q = np.clip(np.rint(np.clip(yd, -1e6, 1e6)), QMIN, p)"),
     ("range fallback", "q = np.where(inr, q, p)", "q = q"),
     ("adam bias correction", "mh = m / (1 - b1 ** step)", "mh = m"),
+    ("f4 normalised by the target box", "F[:, 4] = lg(n1[gS] / max(n1[0], 1e-300))",
+     "F[:, 4] = lg(n1[gS] / np.maximum(n1[gT], 1e-300))"),
+    ("f4 without the root norm", "F[:, 4] = lg(n1[gS] / max(n1[0], 1e-300))", "F[:, 4] = lg(n1[gS])"),
+    ("f5 tail from k >= K/2", "return v.sum(axis=1), v[:, 2 * k > K].sum(axis=1)",
+     "return v.sum(axis=1), v[:, 2 * k >= K].sum(axis=1)"),
+    ("f5 tail not relative", "F[:, 5] = lg(tail[gS] / np.maximum(n1[gS], 1e-300))", "F[:, 5] = lg(tail[gS])"),
+    ("feature order K = p", "K = min(p, FEAT_K)", "K = p"),
+    ("radius floor dropped", "sig = np.maximum(radius, max(radius[0] * 2.0 ** -20, 1e-300))",
+     "sig = np.maximum(radius, 1e-300)"),
 ]
 
 
