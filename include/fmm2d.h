@@ -144,11 +144,15 @@ int fmm2d_workspace_size(fmm2d_handle *h, int64_t n_src, int64_t n_tgt,
  * Phi uses the principal Log in every near-field pair; in the far field it
  * follows the branch of Log(c_T - c_S) of the interacting box centres (the
  * log term of eq. (multipole)), so Phi is defined modulo 2 pi i m_j terms.
- * Errors: FMM2D_EINVAL (n_src < 1, 4^L > n_src, theta outside (0,1), p outside
- * 1..64, NULL src/m/ws, both outputs NULL, bad enum), FMM2D_ENOSPC (workspace
- * too small).  NaN/Inf coordinates are not checked on the device; they make
- * the outputs unspecified.  List overflow is detected on the device and
- * reported by fmm2d_sync. */
+ * Errors returned by this call: FMM2D_EINVAL (n_src < 1, 4^L > n_src, theta
+ * outside (0,1), p outside 1..64, NULL src/m/ws, both outputs NULL, bad enum),
+ * FMM2D_ENOSPC (workspace too small); nothing is launched then.  Errors found
+ * on the device and returned by the next fmm2d_sync / fmm2d_get_stats:
+ * FMM2D_EINVAL if a source or target coordinate or a strength is NaN or
+ * infinite (the evaluation still runs to completion and stays inside its
+ * buffers; its outputs are unspecified), FMM2D_ENOSPC if the interaction lists
+ * overflowed list_cap.  The handle and workspace stay usable after any of
+ * these. */
 int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, const double *m,
                int64_t n_tgt, const double *tgt, const fmm2d_opts *opts,
                double *phi, double *dphi, void *ws, size_t ws_bytes, void *stream);
@@ -162,7 +166,10 @@ int fmm2d_direct(fmm2d_handle *h, int64_t n_src, const double *src, const double
                  uint32_t kernel, double *phi, double *dphi, void *stream);
 
 /* Wait for `stream` and return the device status of the last evaluation:
- * FMM2D_OK, or FMM2D_ENOSPC if its interaction lists overflowed. */
+ * FMM2D_OK; FMM2D_EINVAL if an input coordinate or strength was NaN or
+ * infinite (or FMM2D_P_GIVEN orders were fewer than the weak pairs);
+ * FMM2D_ENOSPC if its interaction lists overflowed.  The status is cleared by
+ * the next fmm2d_eval. */
 int fmm2d_sync(fmm2d_handle *h, void *stream);
 
 /* Device pointers into the workspace describing the tree and lists of the

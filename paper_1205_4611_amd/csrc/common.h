@@ -15,6 +15,7 @@
 #define FMM_ST_LIST_OVERFLOW 1
 #define FMM_ST_ORDERS_SHORT 2   // caller's pair orders shorter than the weak list
 #define FMM_ST_TREE_INCONSISTENT 4 // internal check of the tree build failed
+#define FMM_ST_NONFINITE 8      // a coordinate or strength is NaN or infinite
 #define FMM_LB_TILE 4096         // records per tile of the one-pass partition
 
 // learned truncation order

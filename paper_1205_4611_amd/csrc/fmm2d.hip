@@ -487,6 +487,8 @@ extern "C" int fmm2d_sync(fmm2d_handle *h, void *stream)
     HIPCHK(h, hipStreamSynchronize((hipStream_t)stream));
     int32_t s = 0;
     HIPCHK(h, hipMemcpy(&s, h->d_status, sizeof(s), hipMemcpyDeviceToHost));
+    if (s & FMM_ST_NONFINITE)
+        return fail(h, FMM2D_EINVAL, "a source or target coordinate or a strength is NaN or infinite");
     if (s & FMM_ST_LIST_OVERFLOW)
         return fail(h, FMM2D_ENOSPC, "interaction lists overflowed list_cap; raise fmm2d_opts.list_cap");
     if (s & FMM_ST_ORDERS_SHORT)

@@ -191,14 +191,27 @@ __device__ __forceinline__ uint64_t order_key(double x)
     return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
+// One status bit per wave that saw a non-finite value (an error the host
+// reports after the evaluation; the value itself is then used as 0 where it
+// would steer the tree, so the build stays well formed).
+__device__ __forceinline__ void flag_nonfinite(bool bad, int32_t *status)
+{
+    const uint64_t b = __ballot(bad);
+    if (b && (threadIdx.x & (WAVE - 1)) == __ffsll((unsigned long long)b) - 1) atomicOr(status, FMM_ST_NONFINITE);
+}
+
 __global__ void k_rs_init(const double *__restrict__ pts, int64_t n, int axis,
-                          uint64_t *__restrict__ keys, int32_t *__restrict__ vals)
+                          uint64_t *__restrict__ keys, int32_t *__restrict__ vals, int32_t *__restrict__ status)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
     if (i < n) {
-        keys[i] = order_key(pts[2 * i + axis]);
+        double x = pts[2 * i + axis];
+        bad = !isfinite(x);
+        keys[i] = order_key(bad ? 0.0 : x);
         vals[i] = (int32_t)i;
     }
+    flag_nonfinite(bad, status);
 }
 
 // Per-block digit histogram of one pass: hist[digit][block].
@@ -406,6 +419,7 @@ __global__ void k_rs_decode(const uint64_t *__restrict__ keys, const int32_t *__
         double x;
         if (k == 0x8000000000000000ull) {
             x = pts[2 * min(max((int64_t)order[i], (int64_t)0), n - 1) + axis];
+            if (!isfinite(x)) x = 0.0; // a non-finite coordinate took the key of 0
         } else {
             const uint64_t u = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
             x = __longlong_as_double((long long)u);
@@ -419,10 +433,10 @@ __global__ void k_rs_decode(const uint64_t *__restrict__ keys, const int32_t *__
 // NULL, the coordinates in that order into coord.
 static hipError_t presort(const double *pts, int64_t n, int axis, uint64_t *k0, uint64_t *k1,
                           int32_t *v0, int32_t *v1, int32_t *hist, int32_t *bsum, int32_t *out,
-                          double *coord, hipStream_t st, int32_t *rank = nullptr)
+                          double *coord, int32_t *status, hipStream_t st, int32_t *rank = nullptr)
 {
     if (n <= 0) return hipSuccess;
-    k_rs_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pts, n, axis, k0, v0);
+    k_rs_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pts, n, axis, k0, v0, status);
     hipError_t e = radix_sort(n, 8, k0, k1, v0, v1, hist, bsum, out, st, rank);
     if (e != hipSuccess || !coord) return e;
     // an even number of passes leaves the sorted keys in k0
@@ -478,6 +492,10 @@ __global__ void k_trec_init(const double *__restrict__ pts, const int32_t *__res
         pt_rec r;
         r.x = pts[2 * (int64_t)v];
         r.y = pts[2 * (int64_t)v + 1];
+        // (non-finite coordinates are flagged by the presort; as 0 they
+        // cannot make a rectangle or a split comparison NaN)
+        if (!isfinite(r.x)) r.x = 0.0;
+        if (!isfinite(r.y)) r.y = 0.0;
         r.idx = v;
         r.seg = 0;
         out[i] = r;
@@ -1111,6 +1129,7 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
         const double2 mm = reinterpret_cast<const double2 *>(a.m)[j];
         a.srcs[pos] = make_double4(a.src[2 * j], a.src[2 * j + 1], mm.x, mm.y);
         if (a.m32) a.m32[pos] = make_float2((float)mm.x, (float)mm.y);
+        flag_nonfinite(!(isfinite(mm.x) && isfinite(mm.y)), a.status);
     }
 }
 
@@ -1411,14 +1430,18 @@ __global__ void k_lists_root(int32_t *woff, int32_t *soff, int32_t *sidx, int32_
 __global__ void k_gather(const double *__restrict__ src, const double *__restrict__ m,
                          const int32_t *__restrict__ perm, int64_t ns, double4 *__restrict__ srcs,
                          float2 *__restrict__ m32, const double *__restrict__ tgt,
-                         const int32_t *__restrict__ tperm, int64_t nt, double2 *__restrict__ tgts)
+                         const int32_t *__restrict__ tperm, int64_t nt, double2 *__restrict__ tgts,
+                         int32_t *__restrict__ status)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
     if (i < ns) {
         const int64_t j = min(max((int64_t)perm[i], (int64_t)0), ns - 1);
         srcs[i] = make_double4(src[2 * j], src[2 * j + 1], m[2 * j], m[2 * j + 1]);
         if (m32) m32[i] = make_float2((float)m[2 * j], (float)m[2 * j + 1]);
+        bad = !(isfinite(m[2 * j]) && isfinite(m[2 * j + 1]));
     }
+    flag_nonfinite(bad, status);
     if (i < nt) {
         const int64_t j = min(max((int64_t)tperm[i], (int64_t)0), nt - 1);
         tgts[i] = make_double2(tgt[2 * j], tgt[2 * j + 1]);
@@ -1481,20 +1504,20 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         int32_t *vy0 = reinterpret_cast<int32_t *>(ky1 + ns), *vy1 = vy0 + ns;
         CK(hipEventRecord(a.ev_fork, st));
         CK(hipStreamWaitEvent(a.side, a.ev_fork, 0));
-        CK(presort(a.src, ns, 1, ky0, ky1, vy0, vy1, WS(int32_t, lay.hist2), bsum, py, ys, a.side, ryo));
-        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st, rxo));
+        CK(presort(a.src, ns, 1, ky0, ky1, vy0, vy1, WS(int32_t, lay.hist2), bsum, py, ys, a.status, a.side, ryo));
+        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, a.status, st, rxo));
         CK(hipEventRecord(a.ev_join, a.side));
         CK(hipStreamWaitEvent(st, a.ev_join, 0));
     } else {
-        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, st, rxo));
-        CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, st, ryo));
+        CK(presort(a.src, ns, 0, k0s, k1, v0, v1, hist, bsum, px, xs, a.status, st, rxo));
+        CK(presort(a.src, ns, 1, k0s, k1, v0, v1, hist, bsum, py, ys, a.status, st, ryo));
     }
     k_srec_init<<<nblk256(ns), 256, 0, st>>>(px, py, rxo, ryo, ns, xb[0], yb[0]);
     k_fill_u8<<<nblk256(2 * bstride), 256, 0, st>>>(bxc, 2 * bstride); // the root: both lists in buffer 0
     if (nt) {
-        CK(presort(a.tgt, nt, 0, k0s, k1, v0, v1, hist, bsum, tperm, nullptr, st));
+        CK(presort(a.tgt, nt, 0, k0s, k1, v0, v1, hist, bsum, tperm, nullptr, a.status, st));
         k_trec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[0]);
-        CK(presort(a.tgt, nt, 1, k0s, k1, v0, v1, hist, bsum, tperm, nullptr, st));
+        CK(presort(a.tgt, nt, 1, k0s, k1, v0, v1, hist, bsum, tperm, nullptr, a.status, st));
         k_trec_init<<<nblk256(nt), 256, 0, st>>>(a.tgt, tperm, nt, tl[1]);
     }
     k_root<<<1, 1, 0, st>>>(sstep, (int32_t)ns, tstep, (int32_t)nt);
@@ -1645,7 +1668,7 @@ hipError_t fmm_build_tree(const fmm_tree_args &a, const double *m, hipStream_t s
         int64_t nmax = ns > nt ? ns : nt;
         k_gather<<<nblk256(nmax), 256, 0, st>>>(a.src, m, perm, ns, WS(double4, lay.srcs),
                                                 lay.mixed == 1 ? WS(float2, lay.m32) : nullptr, a.tgt,
-                                                tperm, nt, nt ? WS(double2, lay.tgts) : nullptr);
+                                                tperm, nt, nt ? WS(double2, lay.tgts) : nullptr, a.status);
         CK(hipGetLastError());
     }
     return hipSuccess;

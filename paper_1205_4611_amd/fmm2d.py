@@ -177,6 +177,18 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _output(t, n, dev, name):
+    """A caller-given output must be a contiguous complex128 tensor of n
+    entries on dev (the library writes 16 n bytes); None allocates one."""
+    if t is None:
+        return torch.empty(n, dtype=torch.complex128, device=dev)
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous complex128 tensor" % name)
+    if t.device != dev or t.numel() != n:
+        raise ValueError("%s must have %d entries on %s (has %d on %s)" % (name, n, dev, t.numel(), t.device))
+    return t
+
+
 def _as_points(z, name):
     """complex128 [n] or float64 [n,2] CUDA tensor -> contiguous float64 [n,2]."""
     if z is None:
@@ -238,17 +250,14 @@ class FMM2D:
         order).  Returns (phi, dphi); phi is None for the harmonic kernel.
         check=True synchronises and raises on device-side errors."""
         o = opts if opts is not None else make_opts(**kw)
-        s = _as_points(src, "src")
-        mm = _as_points(m, "m")
-        t = _as_points(tgt, "tgt")
+        s, mm, t = self._inputs(src, m, tgt)
         ns = s.shape[0]
         nt = ns if t is None else t.shape[0]
         dev = s.device
         log = o.kernel == KERNEL["log"]
-        if dphi is None:
-            dphi = torch.empty(nt, dtype=torch.complex128, device=dev)
-        if log and phi is None:
-            phi = torch.empty(nt, dtype=torch.complex128, device=dev)
+        dphi = _output(dphi, nt, dev, "dphi")
+        if log:
+            phi = _output(phi, nt, dev, "phi")
         nbytes = self.workspace_size(ns, 0 if t is None else nt, o)
         ws = self._workspace(nbytes)
         stream = torch.cuda.current_stream(dev).cuda_stream
@@ -268,12 +277,24 @@ class FMM2D:
         if rc != OK:
             raise self._err(rc)
 
-    def direct(self, src, m, tgt=None, tsel=None, kernel="log"):
-        """Device direct sum of Phi, Phi' over all sources (optionally at the
-        targets tsel, an int64 CUDA tensor).  Returns (phi, dphi)."""
+    def _inputs(self, src, m, tgt):
+        """Points and strengths as contiguous float64 [n,2] tensors on this
+        handle's device, with one strength per source."""
         s = _as_points(src, "src")
         mm = _as_points(m, "m")
         t = _as_points(tgt, "tgt")
+        want = torch.device("cuda", self.device)
+        for x, nme in ((s, "src"), (mm, "m"), (t, "tgt")):
+            if x is not None and x.device != want:
+                raise ValueError("%s is on %s, the handle on %s" % (nme, x.device, want))
+        if mm.shape[0] != s.shape[0]:
+            raise ValueError("m has %d entries for %d sources" % (mm.shape[0], s.shape[0]))
+        return s, mm, t
+
+    def direct(self, src, m, tgt=None, tsel=None, kernel="log"):
+        """Device direct sum of Phi, Phi' over all sources (optionally at the
+        targets tsel, an int64 CUDA tensor).  Returns (phi, dphi)."""
+        s, mm, t = self._inputs(src, m, tgt)
         ns = s.shape[0]
         nt = ns if t is None else t.shape[0]
         k = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)

@@ -98,3 +98,22 @@ def test_struct_layout_matches_header(tmp_path):
     # the model size is the trainable part plus mean, 1/std, lo and hi of the features
     assert fmm2d.PORDER_NPARAM == fmm2d.PORDER_HIDDEN * (fmm2d.PORDER_NFEAT + 2) + 1
     assert fmm2d.PORDER_MODEL_FLOATS == fmm2d.PORDER_NPARAM + 4 * fmm2d.PORDER_NFEAT
+
+
+def test_null_handle_and_arguments():
+    """Calls without a handle (or without a device) fail with FMM2D_EINVAL and
+    touch nothing; this needs no GPU."""
+    from paper_1205_4611_amd import fmm2d
+    lib = fmm2d.load()
+    o = fmm2d.make_opts()
+    b = ctypes.c_size_t()
+    assert lib.fmm2d_create(None, 0) == fmm2d.EINVAL
+    h = ctypes.c_void_p()
+    assert lib.fmm2d_create(ctypes.byref(h), -1) == fmm2d.EINVAL and not h.value
+    assert lib.fmm2d_workspace_size(None, 100, 0, ctypes.byref(o), ctypes.byref(b)) == fmm2d.EINVAL
+    assert lib.fmm2d_eval(None, 100, None, None, 0, None, ctypes.byref(o), None, None, None, 0, None) == fmm2d.EINVAL
+    assert lib.fmm2d_direct(None, 100, None, None, 0, None, None, 0, 1, None, None, None) == fmm2d.EINVAL
+    assert lib.fmm2d_sync(None, None) == fmm2d.EINVAL
+    assert lib.fmm2d_get_stats(None, None) == fmm2d.EINVAL
+    assert lib.fmm2d_get_topology(None, None) == fmm2d.EINVAL
+    assert lib.fmm2d_last_error(None) == b"null handle"
