@@ -157,6 +157,25 @@ int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, const double *
                int64_t n_tgt, const double *tgt, const fmm2d_opts *opts,
                double *phi, double *dphi, void *ws, size_t ws_bytes, void *stream);
 
+/* fmm2d_eval without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The workspace is a static device array of
+ * FMM2D_STATIC_WS_BYTES bytes inside the library: every device the library
+ * runs on holds its own copy from the library's first use there (at
+ * fmm2d_create) until the process ends.  The call allocates nothing and takes
+ * the same arguments as fmm2d_eval apart from ws / ws_bytes; it returns
+ * FMM2D_ENOSPC, launching nothing, when fmm2d_workspace_size(...) exceeds
+ * FMM2D_STATIC_WS_BYTES (with the default options about 90,000 sources at the
+ * sources, p = 20).  All calls on one device share that device's array, and
+ * the topology of the last evaluation (fmm2d_get_topology) points into it:
+ * calls that overlap on one device (other streams, other handles, other host
+ * threads) race and must be ordered by the caller.  Every array that must
+ * start at zero is cleared by the call itself. */
+#define FMM2D_STATIC_WS_BYTES ((size_t)64 << 20)
+int fmm2d_eval_static(fmm2d_handle *h, int64_t n_src, const double *src, const double *m,
+                      int64_t n_tgt, const double *tgt, const fmm2d_opts *opts,
+                      double *phi, double *dphi, void *stream);
+
 /* Direct O(N M) summation of the same sums on the device (the near-field
  * kernel applied to all pairs, Sec. 5.3 "break-even").  tsel (device, int64,
  * optional) restricts the evaluation to targets tsel[0..n_sel); outputs are

@@ -6,10 +6,23 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "common.h"
+
+// Workspace of fmm2d_eval_static: a static device array, one copy on every
+// device the library runs on, held until the process ends.  Host code never
+// uses the array's name as an address: each device's copy is looked up once
+// (hipGetSymbolAddress, in fmm2d_create with that device current) and kept in
+// g_scratch_ptr.
+static __device__ __align__(256) char scratch[FMM2D_STATIC_WS_BYTES];
+#define FMM_MAX_DEVICES 64
+static void *g_scratch_ptr[FMM_MAX_DEVICES];
+static std::mutex g_scratch_mu;
 
 struct fmm2d_handle {
     int device;
+    void *scratch;          // this device's copy of `scratch` (device address)
     char err[512];
     int32_t *d_status;      // device status word
     double *d_binom;        // [FMM_BN][FMM_BN]
@@ -215,6 +228,15 @@ extern "C" int fmm2d_create(fmm2d_handle **out, int device)
         }
         e = hipMemcpy(h->d_binom, t, sizeof(double) * FMM_BN * FMM_BN, hipMemcpyHostToDevice);
         free(t);
+    }
+    if (e == hipSuccess && device < FMM_MAX_DEVICES) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void *ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+        }
+        h->scratch = g_scratch_ptr[device];
     }
     for (int i = 0; i <= FMM2D_NPHASE && e == hipSuccess; ++i) e = hipEventCreate(&h->ev[i]);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
@@ -462,6 +484,27 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     h->used_orders = ea.porder;
     h->used_model = use_model;
     return FMM2D_OK;
+}
+
+extern "C" int fmm2d_eval_static(fmm2d_handle *h, int64_t n_src, const double *src, const double *m,
+                                 int64_t n_tgt, const double *tgt, const fmm2d_opts *opts, double *phi,
+                                 double *dphi, void *stream)
+{
+    if (!h) return FMM2D_EINVAL;
+    h->err[0] = 0;
+    if (!h->scratch)
+        return fail(h, FMM2D_EINVAL, "no static workspace on device %d (devices 0..%d only)", h->device,
+                    FMM_MAX_DEVICES - 1);
+    size_t need = 0;
+    int rc = fmm2d_workspace_size(h, n_src, tgt ? n_tgt : 0, opts, &need);
+    if (rc) return rc;
+    if (need > (size_t)FMM2D_STATIC_WS_BYTES)
+        return fail(h, FMM2D_ENOSPC,
+                    "fmm2d_eval_static: this problem needs %zu bytes of workspace, more than the %zu of the "
+                    "static workspace; use fmm2d_eval with a caller workspace",
+                    need, (size_t)FMM2D_STATIC_WS_BYTES);
+    return fmm2d_eval(h, n_src, src, m, n_tgt, tgt, opts, phi, dphi, h->scratch, (size_t)FMM2D_STATIC_WS_BYTES,
+                      stream);
 }
 
 extern "C" int fmm2d_direct(fmm2d_handle *h, int64_t n_src, const double *src, const double *m, int64_t n_tgt,

@@ -19,6 +19,7 @@ OK, EINVAL, ENOSPC, EHIP, ENOMODEL = 0, -1, -2, -3, -4
 KERNEL = {"log": 1, "harmonic": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "mixed_far": 2}
 PORDER = {"fixed": 0, "learned": 1, "given": 2}
+STATIC_WS_BYTES = 64 << 20  # FMM2D_STATIC_WS_BYTES: the workspace of fmm2d_eval_static
 FLAG_TIMING = 1
 FLAG_REQUIRE_MODEL = 2
 FLAG_LEAF_SWAP = 4
@@ -35,7 +36,7 @@ PORDER_QMIN = 4
 
 #: every symbol include/fmm2d.h declares
 EXPORTS = ("fmm2d_default_opts", "fmm2d_create", "fmm2d_destroy", "fmm2d_last_error",
-           "fmm2d_nlevels", "fmm2d_workspace_size", "fmm2d_eval", "fmm2d_direct",
+           "fmm2d_nlevels", "fmm2d_workspace_size", "fmm2d_eval", "fmm2d_eval_static", "fmm2d_direct",
            "fmm2d_sync", "fmm2d_get_topology", "fmm2d_get_stats", "fmm2d_get_times",
            "fmm2d_set_porder_model", "fmm2d_set_pair_orders", "fmm2d_pair_features",
            "fmm2d_pair_labels", "fmm2d_mlp_work_size", "fmm2d_mlp_forward", "fmm2d_mlp_grad",
@@ -113,6 +114,8 @@ def load():
     lib.fmm2d_workspace_size.restype = ctypes.c_int
     lib.fmm2d_eval.argtypes = [P, i64, P, P, i64, P, ctypes.POINTER(Opts), P, P, P, ctypes.c_size_t, P]
     lib.fmm2d_eval.restype = ctypes.c_int
+    lib.fmm2d_eval_static.argtypes = [P, i64, P, P, i64, P, ctypes.POINTER(Opts), P, P, P]
+    lib.fmm2d_eval_static.restype = ctypes.c_int
     lib.fmm2d_direct.argtypes = [P, i64, P, P, i64, P, P, i64, u32, P, P, P]
     lib.fmm2d_direct.restype = ctypes.c_int
     lib.fmm2d_sync.argtypes = [P, P]
@@ -265,6 +268,29 @@ class FMM2D:
         rc = self.lib.fmm2d_eval(self.h, ns, _ptr(s), _ptr(mm), nt if t is not None else 0, _ptr(t),
                                  ctypes.byref(o), _ptr(phi) if log else None, _ptr(dphi), _ptr(ws),
                                  ws.numel(), ctypes.c_void_p(stream))
+        if rc != OK:
+            raise self._err(rc)
+        if check:
+            self.sync()
+        return (phi if log else None), dphi
+
+    def eval_static(self, src, m, tgt=None, *, opts=None, phi=None, dphi=None, check=True, **kw):
+        """As eval, in the library's static workspace (fmm2d_eval_static):
+        no workspace tensor is allocated."""
+        o = opts if opts is not None else make_opts(**kw)
+        s, mm, t = self._inputs(src, m, tgt)
+        ns = s.shape[0]
+        nt = ns if t is None else t.shape[0]
+        dev = s.device
+        log = o.kernel == KERNEL["log"]
+        dphi = _output(dphi, nt, dev, "dphi")
+        if log:
+            phi = _output(phi, nt, dev, "phi")
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self._keep = (s, mm, t)
+        rc = self.lib.fmm2d_eval_static(self.h, ns, _ptr(s), _ptr(mm), nt if t is not None else 0, _ptr(t),
+                                        ctypes.byref(o), _ptr(phi) if log else None, _ptr(dphi),
+                                        ctypes.c_void_p(stream))
         if rc != OK:
             raise self._err(rc)
         if check:
