@@ -55,18 +55,23 @@ def _reject_fn(rng, n, draw):
     return pts
 
 
-def points(dist: str, n: int, seed: int) -> np.ndarray:
-    """n points of distribution `dist` as a complex128 array (x + iy)."""
+def points(dist: str, n: int, seed: int, shape_seed: int | None = None) -> np.ndarray:
+    """n points of distribution `dist` as a complex128 array (x + iy).  For
+    the cluster distributions the cluster centres and widths are drawn first;
+    shape_seed (default: seed) draws them from a generator of their own, so
+    that an independent draw of the same distribution (the same clusters,
+    other points) takes the shape seed of the first draw."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    srng = rng if shape_seed is None else np.random.Generator(np.random.PCG64(shape_seed))
     if dist == "uniform":
         xy = rng.random((n, 2))
     elif dist == "gauss10":
-        cen = rng.uniform(0.1, 0.9, size=(10, 2))
-        sig = rng.uniform(0.01, 0.05, size=10)
+        cen = srng.uniform(0.1, 0.9, size=(10, 2))
+        sig = srng.uniform(0.01, 0.05, size=10)
         xy = _reject_gaussians(rng, n, cen, sig)
     elif dist == "clusters":
-        cen = rng.random((20, 2))
-        sig = rng.uniform(0.002, 0.05, size=20)
+        cen = srng.random((20, 2))
+        sig = srng.uniform(0.002, 0.05, size=20)
         xy = _reject_gaussians(rng, n, cen, sig)
     elif dist == "circle":
         ph = rng.uniform(0.0, 2.0 * np.pi, size=n)
@@ -122,9 +127,12 @@ PORDER_VAL_SEED = 15
 # The measured workloads: (name, sources, separate targets or None, seeds).
 WORKLOADS = {
     "uniform10k": dict(dist="uniform", n=10_000, seed=1, mseed=101, nd=40, tgt=None),
-    "uniform1M": dict(dist="uniform", n=1 << 20, seed=2, mseed=102, nd=45, tgt=("uniform", 102 + 100)),
-    "gauss10_1M": dict(dist="gauss10", n=1 << 20, seed=3, mseed=103, nd=45, tgt=("gauss10", 103 + 100)),
-    "circle1M": dict(dist="circle", n=1 << 20, seed=4, mseed=104, nd=45, tgt=("circle", 104 + 100)),
+    "uniform1M": dict(dist="uniform", n=1 << 20, seed=2, mseed=102, nd=45, tgt=("uniform", 102 + 100),
+                      sel_seed=21),
+    "gauss10_1M": dict(dist="gauss10", n=1 << 20, seed=3, mseed=103, nd=45, tgt=("gauss10", 103 + 100),
+                       sel_seed=22),
+    "circle1M": dict(dist="circle", n=1 << 20, seed=4, mseed=104, nd=45, tgt=("circle", 104 + 100),
+                     sel_seed=23),
     "clusters4M": dict(dist="clusters", n=1 << 22, seed=5, mseed=105, nd=45, tgt=None, sel_seed=7),
     "spiral16M": dict(dist="spiral", n=1 << 24, seed=6, mseed=106, nd=45, tgt=None, sel_seed=8),
 }
@@ -132,13 +140,14 @@ WORKLOADS = {
 
 def workload(name: str, n: int | None = None):
     """(src, m, tgt) for a named workload; n overrides the size (same recipe).
-    Targets of the separate-target workloads reuse the source distribution
-    with an independent draw (its own seed)."""
+    Targets of the separate-target workloads are an independent draw of the
+    source distribution: the same clusters (shape seed of the sources), their
+    own point seed."""
     w = WORKLOADS[name]
     n = w["n"] if n is None else int(n)
     src = points(w["dist"], n, w["seed"])
     m = strengths(n, w["mseed"])
     tgt = None
     if w["tgt"] is not None:
-        tgt = points(w["tgt"][0], n, w["tgt"][1])
+        tgt = points(w["tgt"][0], n, w["tgt"][1], shape_seed=w["seed"])
     return src, m, tgt
