@@ -40,6 +40,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_k_near_clusters4M.txt")
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print("[bench %.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
+T_START = time.perf_counter()
+
+
 def near_flops(st, n, p):
     """Algorithmic flops of the near-field kernel (one launch): per P2P pair
     16 (w = y - x: 2, |w|^2: 3, 1/|w|^2: 1, m conj(w): 6, scale: 2,
@@ -80,8 +88,9 @@ def run_path(f, fmm2d, src, m, p, precision, porder, steps, warmup, phase_steps)
     opts = fmm2d.make_opts(timing=False, **kw)
     topts = fmm2d.make_opts(timing=True, **kw)
     out = None
-    for _ in range(warmup):
+    for i in range(warmup):
         out = f.eval(src, m, opts=opts, check=True)
+        progress("  warm-up step %d done" % i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -112,25 +121,120 @@ def errors(f, src, m, dphi, sel):
             "pt_q999": torch.quantile(r.float(), 0.999).item()}
 
 
-def cpu_baseline(n_sample: int, p: int):
-    """The oracle (plain C, FP64, OpenMP over the host cores) on a bounded
-    sample of the same workload: the same distribution at n_sample points,
-    tree + lists + evaluation with the swapped leaf criterion."""
+# The other measured workloads (one row each in "workloads"): every one runs
+# the plain FP64 FMM at TOL 1e-6 (p = 20; the 10k case at p = 17, N_d = 40, as
+# in the paper's operating point) and the 1M and 16M sets also at TOL 1e-10
+# (p = 34); the 16M spiral also with learned orders.  Errors are pointwise
+# against the device FP64 direct sum at 10,000 seeded targets.
+EXTRA = (
+    ("uniform10k", "log", [("fp64_p17", 17, "fixed")]),
+    ("uniform1M", "log", [("fp64_tol1e-6", 20, "fixed"), ("fp64_tol1e-10", 34, "fixed")]),
+    ("gauss10_1M", "log", [("fp64_tol1e-6", 20, "fixed"), ("fp64_tol1e-10", 34, "fixed")]),
+    ("circle1M", "log", [("fp64_tol1e-6", 20, "fixed"), ("fp64_tol1e-10", 34, "fixed")]),
+    ("spiral16M", "harmonic", [("fp64_tol1e-6", 20, "fixed"), ("learned_tol1e-6", 20, "learned"),
+                               ("fp64_tol1e-10", 34, "fixed")]),
+)
+
+
+def run_workload(f, fmm2d, workloads, name, kernel, runs, steps, warmup):
+    """Timed steps of one workload per (label, p, order policy); Mparticles/s
+    counts sources plus separate evaluation points."""
+    import torch
+    w = workloads.WORKLOADS[name]
+    src, m, tgt = workloads.workload(name)
+    ns, nt = len(src), (0 if tgt is None else len(tgt))
+    ds, dm = torch.from_numpy(src).cuda(), torch.from_numpy(m).cuda()
+    dt = None if tgt is None else torch.from_numpy(tgt).cuda()
+    nout = nt or ns
+    sel = torch.from_numpy(workloads.sample_indices(nout, 10_000, w.get("sel_seed", 9))).cuda()
+    ref = None
+    rows = {}
+    for label, p, porder in runs:
+        progress("  %s %s" % (name, label))
+        opts = fmm2d.make_opts(p=p, levels=-1, leaf_target=w["nd"], kernel=kernel, porder=porder,
+                               swap=tgt is None)
+        for _ in range(warmup):
+            out = f.eval(ds, dm, dt, opts=opts, check=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = f.eval(ds, dm, dt, opts=opts, check=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        f.sync()
+        st = f.stats()
+        if ref is None:
+            _, ref = f.direct(ds, dm, dt, tsel=sel, kernel="harmonic")
+        e = (out[1][sel] - ref).abs()
+        rows[label] = {"value": (ns + nt) / (ms * 1e-3) / 1e6, "ms_per_step": ms, "p": p, "porder": porder,
+                       "levels": fmm2d.nlevels(ns, w["nd"]), "used_model": st["used_model"],
+                       "err_pt": (e / ref.abs()).max().item(), "err_nrm": (e.max() / ref.abs().max()).item()}
+    return {"n_src": ns, "n_tgt": nt, "kernel": kernel, "dist": w["dist"], "runs": rows}
+
+
+def with_copies(f, fmm2d, src, m, p, steps):
+    """Milliseconds per step including the host-to-device copy of the inputs
+    and the device-to-host copy of Phi' (pinned host buffers), the paper's
+    'total' (Sec. 5): learned orders, FP64, as the headline."""
+    import torch
+    hs = torch.view_as_real(src.cpu()).contiguous().pin_memory()
+    hm = torch.view_as_real(m.cpu()).contiguous().pin_memory()
+    hout = torch.empty(src.numel(), dtype=torch.complex128).pin_memory()
+    ds, dm = torch.empty_like(hs, device="cuda"), torch.empty_like(hm, device="cuda")
+    opts = fmm2d.make_opts(p=p, levels=-1, leaf_target=45, kernel="harmonic", porder="learned", swap=True)
+    out = None
+    for i in range(steps + 1):
+        if i == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        ds.copy_(hs, non_blocking=True)
+        dm.copy_(hm, non_blocking=True)
+        out = f.eval(ds, dm, opts=opts, check=False)
+        hout.copy_(out[1], non_blocking=True)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def _oracle_run(n_sample: int, p: int, so_path: str) -> float:
+    """Seconds of the oracle FMM (tree, lists, evaluation with the swapped
+    leaf criterion; FP64, harmonic, fixed order) on n_sample points of the
+    benchmark distribution, on the oracle build at so_path."""
     import oracle
     from paper_1205_4611_amd import workloads
-    oracle.build()
     w = workloads.WORKLOADS[WORKLOAD]
     src = workloads.points(w["dist"], n_sample, w["seed"])
     m = workloads.strengths(n_sample, w["mseed"])
     L = oracle.nlevels(n_sample, 45)
-    t0 = time.perf_counter()
-    T = oracle.Tree(src, L, swap=True)
-    T.eval(m, p, oracle.KERNEL_HARMONIC)
-    dt = time.perf_counter() - t0
+    with oracle.variant(so_path):
+        t0 = time.perf_counter()
+        T = oracle.Tree(src, L, swap=True)
+        T.eval(m, p, oracle.KERNEL_HARMONIC)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(n_sample: int, n_single: int, p: int):
+    """The oracle (plain C, FP64, OpenMP) built for this host with -O3
+    -march=native, timed on all the threads OpenMP uses here on n_sample
+    points of the benchmark distribution, and in a child process on one
+    thread on n_single points (the paper's serial CPU figure)."""
+    import subprocess
+    import tempfile
+    import oracle
+    so = os.path.join(tempfile.mkdtemp(prefix="orc_native_"), "liborc_native.so")
+    oracle.build_native(so)
+    dt = _oracle_run(n_sample, p, so)
     cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count()
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import sys; sys.path.insert(0, %r); import bench; print(bench._oracle_run(%d, %d, %r))"
+            % (HERE, n_single, p, so))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    dt1 = float(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else float("nan")
     return {"value": n_sample / dt / 1e6, "unit": "Mparticles/s", "cores": cores, "kind": "oracle",
-            "sample": "oracle FMM (tree, lists, evaluation; FP64, p=%d, harmonic, fixed order) on %d points "
-                      "of the same 20-cluster distribution: %.1f s wall" % (p, n_sample, dt)}
+            "sample": "oracle FMM (tree, lists, evaluation; FP64, p=%d, harmonic, fixed order, swapped leaf "
+                      "criterion; gcc -O3 -march=native) on %d points of the same 20-cluster distribution: "
+                      "%.1f s wall on %d threads" % (p, n_sample, dt, cores),
+            "single_thread": {"value": n_single / dt1 / 1e6, "unit": "Mparticles/s", "cores": 1,
+                              "sample": "the same on %d points, one thread: %.1f s" % (n_single, dt1)}}
 
 
 def copy_calibration(nbytes: int, reps: int):
@@ -153,9 +257,12 @@ def main():
     ap.add_argument("--p", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
+    ap.add_argument("--cpu-single-sample", type=int, default=1 << 19)
     ap.add_argument("--paths", default="headline,fp64,far32,mixed")
     ap.add_argument("--phase-steps", type=int, default=5,
                     help="steps with per-phase events (run in order on one stream) after the timed ones")
+    ap.add_argument("--workloads", default=",".join(e[0] for e in EXTRA),
+                    help="other measured workloads to report (comma list, empty for none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -186,6 +293,7 @@ def main():
         raise SystemExit("--paths must include headline and fp64")
     res = {}
     for name in names:
+        progress("path %s" % name)
         prec, porder = spec[name]
         out, ms, ph, st = run_path(f, fmm2d, src, m, args.p, prec, porder, args.steps, args.warmup,
                                    args.phase_steps)
@@ -235,8 +343,21 @@ def main():
                      "kernel": "k_near (P2P + M2P, FP64)", "flops_per_launch": flops,
                      "avg_launch_ms": p2p_ms},
     }
+    progress("steps with host copies")
+    line["ms_per_step_with_copies"] = with_copies(f, fmm2d, src, m, args.p, max(3, args.steps // 2))
+    line["with_copies_note"] = ("host-to-device copy of sources and strengths and device-to-host copy of Phi' "
+                                "(pinned host memory) around each headline step")
+    wl = [x for x in args.workloads.split(",") if x]
+    if wl:
+        line["workloads"] = {}
+        for name, kernel, runs in EXTRA:
+            if name in wl:
+                progress("workload %s" % name)
+                line["workloads"][name] = run_workload(f, fmm2d, workloads, name, kernel, runs,
+                                                       max(3, args.steps // 2), 2)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.p)
+        progress("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.cpu_single_sample, args.p)
     print(json.dumps(line))
 
 

@@ -53,6 +53,18 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_native(out_path: str) -> str:
+    """A copy of the oracle compiled for the host it runs on (-O3
+    -march=native, still IEEE FP64 without contraction): the timed CPU
+    baseline.  Built where it runs, since the host may differ from the build
+    machine."""
+    tmp = out_path + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fPIC", "-shared", "-std=gnu11", "-ffp-contract=off",
+                           "-fno-fast-math", "-fopenmp", _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, out_path)
+    return out_path
+
+
 def _load():
     global _lib
     if _lib is not None:

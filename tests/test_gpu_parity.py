@@ -182,6 +182,39 @@ def test_fmm_matches_oracle_fmm(fmm, orc, name, p, swap, kernel):
         assert nrm(host(gp), rp) < 1e-12
 
 
+@pytest.mark.parametrize("kernel", ["log", "harmonic"])
+@pytest.mark.parametrize("p,swap", [(50, False), (64, True), (64, False)])
+def test_high_orders_match_oracle(fmm, orc, p, swap, kernel):
+    """Orders up to the library's maximum (64: two row tiles more than at
+    p = 20 and the widest k-step bodies of the M2L kernel) against the
+    oracle FMM at equal p and lists."""
+    src, tgt, L = _case("clusters20k" if swap else "gauss10_targets")
+    m = workloads.strengths(len(src), 87)
+    k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
+    gp, gd = fmm.eval(dev(src), dev(m), dev(tgt), p=p, levels=L, kernel=kernel, swap=swap)
+    rp, rd = orc.Tree(src, L, tgt=tgt, swap=swap).eval(m, p, k)
+    e = nrm(host(gd), rd)
+    print("p=%d %s swap=%s: dphi normwise %.2e" % (p, kernel, swap, e))
+    assert e < 1e-12
+    if kernel == "log":
+        assert nrm(host(gp), rp) < 1e-12
+
+
+def test_tol_1e10_pointwise(fmm, orc):
+    """TOL 1e-10 (Sec. 5.1) at the a-priori order p = ceil(log 1e-10 / log
+    theta) = 34 (p = 0 with tol given): 10,000 uniform sources, Phi' pointwise
+    against the compensated direct sum."""
+    src = workloads.points("uniform", 10_000, 1)
+    m = workloads.strengths(10_000, 101)
+    L = orc.nlevels(10_000, 40)
+    _, gd = fmm.eval(dev(src), dev(m), p=0, tol=1e-10, levels=L, kernel="harmonic")
+    assert fmm.topology()["p"] == 34
+    _, rd = orc.direct(src, m, kernel=orc.KERNEL_HARMONIC)
+    e = float(np.max(np.abs(host(gd) - rd) / np.abs(rd)))
+    print("TOL 1e-10 at p=34: pointwise %.2e" % e)
+    assert e < 1e-10
+
+
 def test_l0_is_direct(fmm, orc):
     src = workloads.points("clusters", 700, 77)
     m = workloads.strengths(700, 78)
@@ -273,8 +306,9 @@ def test_error_paths(fmm):
 @pytest.mark.parametrize("name", ["clusters20k", "gauss10_targets"])
 def test_mixed_close_to_fp64(fmm, orc, name, kernel):
     """FP32 P2P and FP32 M2L (radius-scaled, MFMA) against the FP64 oracle FMM
-    at the same order and lists: the FP32 rounding stays near 1e-7 relative
-    to the potential's scale (normwise)."""
+    at the same order and lists: a check of the FP32 kernels, whose rounding
+    stays near 1e-7 relative to the potential's scale (normwise).  It is not
+    the TOL metric: test_mixed_meets_tol_pointwise states that one."""
     src, tgt, L = _case(name)
     m = workloads.strengths(len(src), 85)
     k = orc.KERNEL_LOG if kernel == "log" else orc.KERNEL_HARMONIC
@@ -288,6 +322,24 @@ def test_mixed_close_to_fp64(fmm, orc, name, kernel):
         e_p = nrm(host(gp), rp)
         print("mixed %s %s: phi normwise %.2e" % (name, kernel, e_p))
         assert e_p < 2e-6
+
+
+@pytest.mark.xfail(strict=False, reason="the FP32 far field and near field round at ~1e-7 of a typical "
+                   "contribution, more than 1e-6 of |Phi'| at targets where Phi' nearly cancels: the mixed path "
+                   "misses TOL 1e-6 pointwise on clustered data")
+@pytest.mark.parametrize("precision", ["mixed", "mixed_far"])
+def test_mixed_meets_tol_pointwise(fmm, orc, precision):
+    """The mixed-precision paths against the TOL 1e-6 of Sec. 5.1 in its own
+    metric (pointwise relative error of Phi' against the direct sum) on
+    40,000 clustered sources at p = 20."""
+    src = workloads.points("clusters", 40_000, 88)
+    m = workloads.strengths(40_000, 89)
+    L = orc.nlevels(40_000, 45)
+    _, gd = fmm.eval(dev(src), dev(m), p=20, levels=L, kernel="harmonic", swap=True, precision=precision)
+    _, rd = orc.direct(src, m, kernel=orc.KERNEL_HARMONIC)
+    e = float(np.max(np.abs(host(gd) - rd) / np.abs(rd)))
+    print("%s: pointwise %.2e" % (precision, e))
+    assert e < 1e-6
 
 
 def test_heavy_boxes_match_oracle(fmm, orc):
