@@ -237,6 +237,38 @@ def cpu_baseline(n_sample: int, n_single: int, p: int):
                               "sample": "the same on %d points, one thread: %.1f s" % (n_single, dt1)}}
 
 
+def db_summary(paths, counters: bool):
+    """Text summary of rocprofv3 result databases (rocpd SQLite): per kernel
+    the dispatches, total and average duration; with counters, per (kernel,
+    grid size) the average of every collected counter per dispatch."""
+    import collections
+    import sqlite3
+    for db in paths:
+        c = sqlite3.connect(db)
+        print("# %s" % db)
+        if not counters:
+            agg = collections.defaultdict(lambda: [0, 0.0])
+            for name, du in c.execute("select name, duration from kernels"):
+                agg[name][0] += 1
+                agg[name][1] += du / 1e3
+            tot = sum(v[1] for v in agg.values()) or 1.0
+            print("%-70s %6s %11s %10s %6s" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
+            for name, (n, us) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+                print("%-70s %6d %11.3f %10.1f %6.2f" % (name[:70], n, us / 1e3, us / n, 100.0 * us / tot))
+            continue
+        agg = collections.defaultdict(lambda: collections.defaultdict(float))
+        disp = collections.defaultdict(dict)
+        q = "select kernel_name, grid_size, dispatch_id, counter_name, value, duration from counters_collection"
+        for k, g, d, cn, v, du in c.execute(q):
+            agg[(k, g)][cn] += v
+            disp[(k, g)][d] = du
+        for key in sorted(agg, key=lambda kk: -sum(disp[kk].values())):
+            n = len(disp[key])
+            vals = " ".join("%s=%.4g" % (cn, v / n) for cn, v in sorted(agg[key].items()))
+            print("%-60s grid=%-9d n=%-3d avg_us=%-9.1f %s" % (key[0][:60], key[1], n,
+                                                                 sum(disp[key].values()) / n / 1e3, vals))
+
+
 def copy_calibration(nbytes: int, reps: int):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -265,7 +297,14 @@ def main():
                     help="other measured workloads to report (comma list, empty for none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES bytes (counter calibration)")
+    ap.add_argument("--kernel-stats", nargs="+", metavar="DB",
+                    help="only print per-kernel statistics of rocprofv3 result databases")
+    ap.add_argument("--counter-stats", nargs="+", metavar="DB",
+                    help="only print per-kernel counter averages of rocprofv3 --pmc result databases")
     args = ap.parse_args()
+    if args.kernel_stats or args.counter_stats:
+        db_summary(args.kernel_stats or args.counter_stats, counters=bool(args.counter_stats))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
