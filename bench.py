@@ -9,11 +9,14 @@ sources, with inputs resident in HBM.  theta = 1/2, levels from eq.
 ceil(log 1e-6 / log theta)).
 
 Paths (each timed over the same K steps after W warm-up steps):
-  headline   learned per-pair M2L orders (storage order p), FP64 arithmetic
-  fp64       the plain FP64 FMM at the fixed order p (the baseline)
+  learned    learned per-pair M2L orders (storage order p), FP64 arithmetic
+  fp64       the plain FP64 FMM at the fixed order p (the metric's baseline)
   far32      FP32 M2L contraction (radius-scaled) + learned orders (ablation)
-  mixed      FP32 near field and FP32 M2L + learned orders (ablation)
-The FP32 variants are reported with their errors: with random complex
+  mixed      FP32 near field and FP32 M2L + learned orders: the metric's
+             mixed-precision + learned-order form
+`value` is the throughput of the fastest path whose pointwise error meets
+the tolerance; every path is listed under "metric_paths" with its speedup
+over plain FP64 and whether it meets the tolerance.  With random complex
 strengths, FP32 rounding of the far field (~1e-7 of a typical contribution)
 exceeds 1e-6 pointwise at the targets where |Phi'| nearly cancels.
 Each path's error is measured against the device FP64 direct sum at 10,000
@@ -33,6 +36,9 @@ import time
 import numpy as np
 
 METRIC = "Mparticles/s, N=4M clustered, rel.err≤1e-6: mixed+learned-p vs plain FP64 FMM"
+PATH_TEXT = {"fp64": "plain FP64 FMM, fixed order p", "learned": "FP64 arithmetic, learned per-pair M2L orders",
+             "far32": "FP32 M2L contraction (radius-scaled) + learned orders, FP64 elsewhere",
+             "mixed": "mixed precision (FP32 near field and M2L contraction) + learned orders"}
 WORKLOAD = "clusters4M"
 TOL = 1e-6
 FP64_PEAK = 78.6    # TFLOP/s, MI355X FP64 vector
@@ -172,16 +178,17 @@ def run_workload(f, fmm2d, workloads, name, kernel, runs, steps, warmup):
     return {"n_src": ns, "n_tgt": nt, "kernel": kernel, "dist": w["dist"], "runs": rows}
 
 
-def with_copies(f, fmm2d, src, m, p, steps):
+def with_copies(f, fmm2d, src, m, p, steps, path):
     """Milliseconds per step including the host-to-device copy of the inputs
     and the device-to-host copy of Phi' (pinned host buffers), the paper's
-    'total' (Sec. 5): learned orders, FP64, as the headline."""
+    'total' (Sec. 5), for path = (precision, order policy)."""
     import torch
     hs = torch.view_as_real(src.cpu()).contiguous().pin_memory()
     hm = torch.view_as_real(m.cpu()).contiguous().pin_memory()
     hout = torch.empty(src.numel(), dtype=torch.complex128).pin_memory()
     ds, dm = torch.empty_like(hs, device="cuda"), torch.empty_like(hm, device="cuda")
-    opts = fmm2d.make_opts(p=p, levels=-1, leaf_target=45, kernel="harmonic", porder="learned", swap=True)
+    opts = fmm2d.make_opts(p=p, levels=-1, leaf_target=45, kernel="harmonic", precision=path[0], porder=path[1],
+                           swap=True)
     out = None
     for i in range(steps + 1):
         if i == 1:
@@ -290,7 +297,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-single-sample", type=int, default=1 << 19)
-    ap.add_argument("--paths", default="headline,fp64,far32,mixed")
+    ap.add_argument("--paths", default="learned,fp64,far32,mixed")
     ap.add_argument("--phase-steps", type=int, default=5,
                     help="steps with per-phase events (run in order on one stream) after the timed ones")
     ap.add_argument("--workloads", default=",".join(e[0] for e in EXTRA),
@@ -325,11 +332,11 @@ def main():
     model, delta, meta = fmm2d.load_porder_model()
     f.set_porder_model(model, delta)
 
-    spec = {"headline": ("fp64", "learned"), "fp64": ("fp64", "fixed"),
+    spec = {"learned": ("fp64", "learned"), "fp64": ("fp64", "fixed"),
             "far32": ("mixed_far", "learned"), "mixed": ("mixed", "learned")}
-    names = [x for x in args.paths.split(",") if x]
-    if "headline" not in names or "fp64" not in names:
-        raise SystemExit("--paths must include headline and fp64")
+    names = [("learned" if x == "headline" else x) for x in args.paths.split(",") if x]
+    if "fp64" not in names:
+        raise SystemExit("--paths must include fp64 (the baseline of the metric)")
     res = {}
     for name in names:
         progress("path %s" % name)
@@ -341,8 +348,15 @@ def main():
                          mean_order=float((hist * np.arange(args.p + 1)).sum() / max(hist.sum(), 1)),
                          used_model=st["used_model"])
 
-    head, base = res["headline"], res["fp64"]
+    # The value is the fastest path that meets the tolerance (pointwise
+    # relative error <= 1e-6 at the 10,000 sampled sources); every path is
+    # reported with its speedup over plain FP64 and whether it meets it.
+    base = res["fp64"]
+    ok = [k for k in res if res[k]["err"]["pt"] <= TOL]
+    chosen = min(ok, key=lambda k: res[k]["ms"]) if ok else "fp64"
+    head = res[chosen]
     st = head["stats"]
+    mx = res.get("mixed")
     L = fmm2d.nlevels(n, 45)
     flops = near_flops(st, n, args.p)
     p2p_ms = head["phases"]["p2p"]
@@ -362,12 +376,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: N=%d sources, 20 Gaussian clusters, Phi' at the sources" % (WORKLOAD, n),
                    "kernel": "harmonic", "theta": 0.5, "p": args.p, "levels": L, "leaf_target": 45,
-                   "path": "learned per-pair M2L orders, FP64 arithmetic",
+                   "path": PATH_TEXT[chosen],
                    "porder_model": os.path.basename(fmm2d.MODEL_PATH), "delta": delta},
         "err": head["err"],
         "meets_tol": head["err"]["pt"] <= TOL,
         "mean_order": head["mean_order"],
         "speedup_vs_fp64": base["ms"] / head["ms"],
+        "metric_paths": {k: {"path": PATH_TEXT[k], "value": n / (v["ms"] * 1e-3) / 1e6,
+                             "speedup_vs_fp64": base["ms"] / v["ms"], "err_pt": v["err"]["pt"],
+                             "meets_tol": v["err"]["pt"] <= TOL} for k, v in res.items()},
+        "metric_note": ("value: the fastest path within rel.err 1e-6 (%s). The metric's comparison, "
+                        "mixed precision + learned orders against plain FP64: %s"
+                        % (chosen, "not run" if mx is None else
+                           "%.3fx the plain FP64 rate at pointwise error %.2g (%s the tolerance)"
+                           % (base["ms"] / mx["ms"], mx["err"]["pt"],
+                              "meets" if mx["err"]["pt"] <= TOL else "misses"))),
         "phases_ms": head["phases"],
         "phases_note": "per-phase HIP events over %d extra steps that run the phases in order on one stream; "
                        "the timed steps overlap the far field and the y presort with the rest" % args.phase_steps,
@@ -376,16 +399,17 @@ def main():
                    "m2p_evals": st["n_m2p_evals"], "p2l_evals": st["n_p2l_evals"]},
         "paths": {k: {"value": n / (v["ms"] * 1e-3) / 1e6, "ms_per_step": v["ms"], "err": v["err"],
                       "mean_order": v["mean_order"], "used_model": v["used_model"],
-                      "phases_ms": v["phases"]} for k, v in res.items() if k != "headline"},
+                      "phases_ms": v["phases"]} for k, v in res.items() if k != chosen},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK, "traffic": traffic_bytes(),
                      "kernel": "k_near (P2P + M2P, FP64)", "flops_per_launch": flops,
                      "avg_launch_ms": p2p_ms},
     }
     progress("steps with host copies")
-    line["ms_per_step_with_copies"] = with_copies(f, fmm2d, src, m, args.p, max(3, args.steps // 2))
+    line["ms_per_step_with_copies"] = with_copies(f, fmm2d, src, m, args.p, max(3, args.steps // 2),
+                                                  spec[chosen])
     line["with_copies_note"] = ("host-to-device copy of sources and strengths and device-to-host copy of Phi' "
-                                "(pinned host memory) around each headline step")
+                                "(pinned host memory) around each step of the value's path")
     wl = [x for x in args.workloads.split(",") if x]
     if wl:
         line["workloads"] = {}
