@@ -94,7 +94,9 @@ typedef struct fmm2d_opts {
                             p = ceil(log(tol) / log(theta)) (Sec. 2) */
     int32_t levels;      /* tree depth L >= 0 (4^L leaves, 4^L <= n_src);
                             -1 = derive by eq. (Nlevels) from leaf_target */
-    int32_t leaf_target; /* N_d of eq. (Nlevels), the desired sources per leaf */
+    int32_t leaf_target; /* N_d of eq. (Nlevels), the desired sources per leaf;
+                            0 = the value calibrated on MI355X for the order p
+                            (45 for p <= 26, 100 for p >= 27) */
     uint32_t kernel;     /* FMM2D_KERNEL_* */
     uint32_t precision;  /* FMM2D_FP64 or FMM2D_MIXED */
     uint32_t porder;     /* FMM2D_P_FIXED or FMM2D_P_LEARNED */
@@ -104,7 +106,8 @@ typedef struct fmm2d_opts {
 } fmm2d_opts;
 
 /* Fill `o` with the defaults: theta 1/2, tol 1e-6, p 0, levels -1,
- * leaf_target 45 (the optimum reported in Sec. 5.1), LOG, FP64, fixed order. */
+ * leaf_target 0 (calibrated: 45, the optimum Sec. 5.1 reports, up to p = 26),
+ * LOG, FP64, fixed order. */
 void fmm2d_default_opts(fmm2d_opts *o);
 
 typedef struct fmm2d_handle fmm2d_handle;

@@ -74,7 +74,7 @@ extern "C" void fmm2d_default_opts(fmm2d_opts *o)
     o->tol = 1e-6;
     o->p = 0;
     o->levels = -1;
-    o->leaf_target = 45;
+    o->leaf_target = 0;
     o->kernel = FMM2D_KERNEL_LOG;
     o->precision = FMM2D_FP64;
     o->porder = FMM2D_P_FIXED;
@@ -94,6 +94,15 @@ extern "C" int fmm2d_nlevels(int64_t n, int32_t nd)
     }
     return L;
 }
+
+// The leaf target N_d that eq. (Nlevels) uses when fmm2d_opts.leaf_target is
+// 0: the calibration of Sec. 5.1 repeated on MI355X (FP64, harmonic kernel,
+// 20-cluster sources at the sources, N from 2^20 to 2^24, fixed and learned
+// orders): the fastest depth lies in N_d in [40, 79] up to p = 20 and in
+// [80, 159] from p = 27 on (at p = 24 the two depths are within 2%), as the
+// paper finds the optimum growing with p (Sec. 5.2); 45 is also the paper's
+// optimum for its GPU.
+static int32_t calibrated_nd(int p) { return p >= 27 ? 100 : 45; }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -290,8 +299,8 @@ static int resolve(fmm2d_handle *h, int64_t ns, const fmm2d_opts *o, int *L, int
     if (pp < 1 || pp > FMM_PMAX) return fail(h, FMM2D_EINVAL, "p=%d outside 1..%d", pp, FMM_PMAX);
     int LL = o->levels;
     if (LL < 0) {
-        if (o->leaf_target < 1) return fail(h, FMM2D_EINVAL, "leaf_target must be >= 1");
-        LL = fmm2d_nlevels(ns, o->leaf_target);
+        if (o->leaf_target < 0) return fail(h, FMM2D_EINVAL, "leaf_target must be >= 0");
+        LL = fmm2d_nlevels(ns, o->leaf_target > 0 ? o->leaf_target : calibrated_nd(pp));
     }
     if (LL > FMM_MAXL) return fail(h, FMM2D_EINVAL, "levels=%d > %d", LL, FMM_MAXL);
     if (nbox(LL) > ns) return fail(h, FMM2D_EINVAL, "4^L = %lld exceeds n_src = %lld", (long long)nbox(LL), (long long)ns);

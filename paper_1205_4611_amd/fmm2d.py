@@ -157,7 +157,7 @@ def nlevels(n: int, nd: int) -> int:
     return int(load().fmm2d_nlevels(int(n), int(nd)))
 
 
-def make_opts(theta=0.5, tol=1e-6, p=0, levels=-1, leaf_target=45, kernel="log",
+def make_opts(theta=0.5, tol=1e-6, p=0, levels=-1, leaf_target=0, kernel="log",
               precision="fp64", porder="fixed", timing=False, require_model=False,
               list_cap=0, swap=False) -> Opts:
     o = Opts()

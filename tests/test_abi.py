@@ -49,7 +49,7 @@ def test_host_only_calls():
     assert lib.fmm2d_nlevels(0, 45) == -1
     assert lib.fmm2d_mlp_work_size(256) >= 322 * 4
     o = fmm2d.make_opts()
-    assert abs(o.theta - 0.5) < 1e-15 and o.levels == -1 and o.leaf_target == 45
+    assert abs(o.theta - 0.5) < 1e-15 and o.levels == -1 and o.leaf_target == 0
 
 
 LAYOUT_C = r"""

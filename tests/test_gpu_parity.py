@@ -215,6 +215,18 @@ def test_tol_1e10_pointwise(fmm, orc):
     assert e < 1e-10
 
 
+def test_calibrated_leaf_target(fmm):
+    """leaf_target 0 takes the N_d calibrated for the order in eq. (Nlevels):
+    45 up to p = 26, 100 from p = 27."""
+    from paper_1205_4611_amd import fmm2d
+    n = 1 << 21
+    src = dev(workloads.points("uniform", n, 141))
+    m = dev(workloads.strengths(n, 142))
+    for p, nd, L in ((20, 45, 8), (30, 100, 7)):
+        fmm.eval(src, m, p=p, levels=-1, leaf_target=0, kernel="harmonic")
+        assert fmm.topology()["levels"] == fmm2d.nlevels(n, nd) == L, p
+
+
 def test_l0_is_direct(fmm, orc):
     src = workloads.points("clusters", 700, 77)
     m = workloads.strengths(700, 78)
@@ -288,7 +300,7 @@ def test_error_paths(fmm):
     src = dev(workloads.points("uniform", 100, 81))
     m = dev(workloads.strengths(100, 82))
     for kw in (dict(theta=1.5), dict(theta=0.0), dict(p=100), dict(levels=4), dict(p=0, tol=-1.0),
-               dict(leaf_target=0)):
+               dict(leaf_target=-1)):
         with pytest.raises(fmm2d.FMMError) as e:
             fmm.eval(src, m, **kw)
         assert e.value.code == fmm2d.EINVAL, kw
