@@ -14,6 +14,8 @@ Paths (each timed over the same K steps after W warm-up steps):
   far32      FP32 M2L contraction (radius-scaled) + learned orders (ablation)
   mixed      FP32 near field and FP32 M2L + learned orders: the metric's
              mixed-precision + learned-order form
+  mutual     plain FP64 with the mutual near field (each unordered leaf pair
+             evaluated once for both directions)
 `value` is the throughput of the fastest path whose pointwise error meets
 the tolerance; every path is listed under "metric_paths" with its speedup
 over plain FP64 and whether it meets the tolerance.  With random complex
@@ -38,7 +40,8 @@ import numpy as np
 METRIC = "Mparticles/s, N=4M clustered, rel.err≤1e-6: mixed+learned-p vs plain FP64 FMM"
 PATH_TEXT = {"fp64": "plain FP64 FMM, fixed order p", "learned": "FP64 arithmetic, learned per-pair M2L orders",
              "far32": "FP32 M2L contraction (radius-scaled) + learned orders, FP64 elsewhere",
-             "mixed": "mixed precision (FP32 near field and M2L contraction) + learned orders"}
+             "mixed": "mixed precision (FP32 near field and M2L contraction) + learned orders",
+             "mutual": "plain FP64 FMM, fixed order p, mutual near field (each leaf pair once)"}
 WORKLOAD = "clusters4M"
 TOL = 1e-6
 FP64_PEAK = 78.6    # TFLOP/s, MI355X FP64 vector
@@ -83,14 +86,15 @@ def traffic_bytes():
         return None
 
 
-def run_path(f, fmm2d, src, m, p, precision, porder, steps, warmup, phase_steps):
+def run_path(f, fmm2d, src, m, p, precision, porder, steps, warmup, phase_steps, mutual=False):
     """Timed steps as the library runs them by default (the far field and the
     y presort on its side stream, beside the lists and the near field), then
     phase_steps steps with per-phase HIP events, which run the phases one
     after another on one stream: the phase breakdown and the near-field
     kernel time come from those."""
     import torch
-    kw = dict(p=p, levels=-1, leaf_target=45, kernel="harmonic", precision=precision, porder=porder, swap=True)
+    kw = dict(p=p, levels=-1, leaf_target=45, kernel="harmonic", precision=precision, porder=porder, swap=True,
+              mutual=mutual)
     opts = fmm2d.make_opts(timing=False, **kw)
     topts = fmm2d.make_opts(timing=True, **kw)
     out = None
@@ -181,14 +185,14 @@ def run_workload(f, fmm2d, workloads, name, kernel, runs, steps, warmup):
 def with_copies(f, fmm2d, src, m, p, steps, path):
     """Milliseconds per step including the host-to-device copy of the inputs
     and the device-to-host copy of Phi' (pinned host buffers), the paper's
-    'total' (Sec. 5), for path = (precision, order policy)."""
+    'total' (Sec. 5), for path = (precision, order policy, mutual near field)."""
     import torch
     hs = torch.view_as_real(src.cpu()).contiguous().pin_memory()
     hm = torch.view_as_real(m.cpu()).contiguous().pin_memory()
     hout = torch.empty(src.numel(), dtype=torch.complex128).pin_memory()
     ds, dm = torch.empty_like(hs, device="cuda"), torch.empty_like(hm, device="cuda")
     opts = fmm2d.make_opts(p=p, levels=-1, leaf_target=45, kernel="harmonic", precision=path[0], porder=path[1],
-                           swap=True)
+                           swap=True, mutual=path[2])
     out = None
     for i in range(steps + 1):
         if i == 1:
@@ -297,7 +301,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-single-sample", type=int, default=1 << 19)
-    ap.add_argument("--paths", default="learned,fp64,far32,mixed")
+    ap.add_argument("--paths", default="learned,fp64,far32,mixed,mutual")
     ap.add_argument("--phase-steps", type=int, default=5,
                     help="steps with per-phase events (run in order on one stream) after the timed ones")
     ap.add_argument("--workloads", default=",".join(e[0] for e in EXTRA),
@@ -333,7 +337,7 @@ def main():
     f.set_porder_model(model, delta)
 
     spec = {"learned": ("fp64", "learned"), "fp64": ("fp64", "fixed"),
-            "far32": ("mixed_far", "learned"), "mixed": ("mixed", "learned")}
+            "far32": ("mixed_far", "learned"), "mixed": ("mixed", "learned"), "mutual": ("fp64", "fixed")}
     names = [("learned" if x == "headline" else x) for x in args.paths.split(",") if x]
     if "fp64" not in names:
         raise SystemExit("--paths must include fp64 (the baseline of the metric)")
@@ -342,7 +346,7 @@ def main():
         progress("path %s" % name)
         prec, porder = spec[name]
         out, ms, ph, st = run_path(f, fmm2d, src, m, args.p, prec, porder, args.steps, args.warmup,
-                                   args.phase_steps)
+                                   args.phase_steps, mutual=name == "mutual")
         hist = np.array(st["p_hist"][:args.p + 1], np.float64)
         res[name] = dict(ms=ms, phases=ph, stats=st, err=errors(f, src, m, out[1], sel),
                          mean_order=float((hist * np.arange(args.p + 1)).sum() / max(hist.sum(), 1)),
@@ -407,7 +411,7 @@ def main():
     }
     progress("steps with host copies")
     line["ms_per_step_with_copies"] = with_copies(f, fmm2d, src, m, args.p, max(3, args.steps // 2),
-                                                  spec[chosen])
+                                                  spec[chosen] + (chosen == "mutual",))
     line["with_copies_note"] = ("host-to-device copy of sources and strengths and device-to-host copy of Phi' "
                                 "(pinned host memory) around each step of the value's path")
     wl = [x for x in args.workloads.split(",") if x]

@@ -85,6 +85,14 @@ extern "C" {
                                        criterion with the radii interchanged (Sec. 2)
                                        are handled by M2P (larger target box) or P2L
                                        (larger source box) instead of P2P */
+#define FMM2D_FLAG_MUTUAL 8u        /* evaluation at the sources with the harmonic kernel
+                                       in FP64 and at most 64 sources per leaf: each
+                                       unordered pair of near-field leaves is evaluated
+                                       once for both directions (the pair symmetry of
+                                       Sec. 4), with a deterministic sum of the reverse
+                                       parts; ignored otherwise.  Its workspace holds
+                                       list_cap / 16 (at least 4) upper leaf pairs per
+                                       leaf; more is reported as FMM2D_ENOSPC */
 
 typedef struct fmm2d_opts {
     double theta;        /* theta-criterion parameter, in (0,1); Sec. 2 uses 1/2 */

@@ -105,6 +105,8 @@ struct fmm_layout {
     size_t nhw, nhoff, nuleaf, npart; // near-field units of heavy leaves
     int64_t nucap;               // capacity in near-field units
     size_t nsum;                 // near sums per leaf-order target: Phi' [n], then Phi [n] (double2)
+    size_t mut_ucnt, mut_uoff, mut_rev; // mutual near field: upper entries per leaf, their scan, reverse sums
+    int64_t mut_rcap;            // capacity of mut_rev in upper entries
     int64_t hmax;                // capacity in segments
     size_t qw;                   // uint8 order per weak pair, weak-list order
     size_t sw, sp;               // weak pairs sorted by order within a box: source, order
@@ -113,7 +115,7 @@ struct fmm_layout {
 };
 
 int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, int learned,
-                    fmm_layout *lay);
+                    fmm_layout *lay, int mutual);
 
 // --------------------------------------------------------------------------
 // Launchers (defined in the .hip files).  All asynchronous on `st`.
@@ -148,6 +150,8 @@ struct fmm_eval_args {
     int32_t cap;
     int swap;
     int porder;                   // per-pair orders (sorted lists sw/sp) in use
+    int mutual;                   // mutual near field (at the sources, harmonic, FP64, leaves <= 64)
+    int32_t *status;
 };
 hipError_t fmm_p2m(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_m2m(const fmm_eval_args &a, hipStream_t st);

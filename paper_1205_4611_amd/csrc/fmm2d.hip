@@ -106,8 +106,17 @@ static int32_t calibrated_nd(int p) { return p >= 27 ? 100 : 45; }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The mutual near field applies (evaluation at the sources, harmonic, FP64,
+// at most 64 sources per leaf; equal-count splits make every leaf hold at
+// most ceil(ns / 4^L)).
+static int use_mutual(const fmm2d_opts *o, int64_t nt, int64_t ns, int L)
+{
+    return (o->flags & FMM2D_FLAG_MUTUAL) && nt == 0 && o->kernel == FMM2D_KERNEL_HARMONIC &&
+           o->precision == FMM2D_FP64 && (ns + nbox(L) - 1) / nbox(L) <= 64;
+}
+
 int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, int learned,
-                    fmm_layout *lay)
+                    fmm_layout *lay, int mutual)
 {
     memset(lay, 0, sizeof(*lay));
     lay->ns = ns; lay->nt = nt; lay->L = L; lay->p = p; lay->cap = cap;
@@ -204,6 +213,10 @@ int fmm_plan_layout(int64_t ns, int64_t nt, int L, int p, int cap, int mixed, in
     lay->nuleaf = take(4 * lay->nucap);
     lay->npart = take(8 * 4 * 64 * lay->nucap);
     lay->nsum = take(32 * (nt ? nt : ns));
+    lay->mut_rcap = mutual ? lay->nleaf * (cap / 16 > 4 ? cap / 16 : 4) : 0;
+    lay->mut_ucnt = mutual ? take(4 * lay->nleaf) : 0;
+    lay->mut_uoff = mutual ? take(4 * (lay->nleaf + 1)) : 0;
+    lay->mut_rev = mutual ? take(16 * 64 * (size_t)lay->mut_rcap) : 0;
     lay->qw = learned ? take(lay->listcap) : 0;
     lay->sw = learned ? take(4 * lay->listcap) : 0;
     lay->pbox = learned ? take(4 * lay->listcap) : 0;
@@ -320,7 +333,8 @@ extern "C" int fmm2d_workspace_size(fmm2d_handle *h, int64_t n_src, int64_t n_tg
     if (rc) return rc;
     if (n_tgt < 0 || n_tgt > ((int64_t)1 << 30)) return fail(h, FMM2D_EINVAL, "n_tgt out of range");
     fmm_layout lay;
-    fmm_plan_layout(n_src, n_tgt, L, p, cap, (int)opts->precision, opts->porder != FMM2D_P_FIXED, &lay);
+    fmm_plan_layout(n_src, n_tgt, L, p, cap, (int)opts->precision, opts->porder != FMM2D_P_FIXED, &lay,
+                    use_mutual(opts, n_tgt, n_src, L));
     *bytes = lay.total;
     return FMM2D_OK;
 }
@@ -379,7 +393,8 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
                     FMM2D_PORDER_FEAT_K);
     if (use_given && !h->given) return fail(h, FMM2D_EINVAL, "FMM2D_P_GIVEN without fmm2d_set_pair_orders");
     fmm_layout lay;
-    fmm_plan_layout(n_src, nt, L, p, cap, mixed, learned, &lay);
+    const int mutual = use_mutual(opts, nt, n_src, L);
+    fmm_plan_layout(n_src, nt, L, p, cap, mixed, learned, &lay, mutual);
     if (ws_bytes < lay.total)
         return fail(h, FMM2D_ENOSPC, "workspace of %zu bytes < %zu needed", ws_bytes, lay.total);
     hipStream_t st = (hipStream_t)stream;
@@ -410,6 +425,8 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     ea.ns = n_src; ea.nt = nt ? nt : n_src; ea.at_sources = nt == 0;
     ea.ws = w; ea.lay = &lay; ea.binom = h->d_binom; ea.cap = cap; ea.swap = ta.swap;
     ea.porder = use_model || use_given;
+    ea.mutual = mutual;
+    ea.status = h->d_status;
     fmm_porder_args pa = porder_args(h, w, lay, L, p, cap);
     if (use_model) {
         pa.model = h->d_model;

@@ -23,6 +23,7 @@ STATIC_WS_BYTES = 64 << 20  # FMM2D_STATIC_WS_BYTES: the workspace of fmm2d_eval
 FLAG_TIMING = 1
 FLAG_REQUIRE_MODEL = 2
 FLAG_LEAF_SWAP = 4
+FLAG_MUTUAL = 8
 PHASES = ("tree", "lists", "p2m", "m2m", "porder", "m2l", "l2l", "p2l", "p2p", "near_reduce")
 
 # learned order (see include/fmm2d.h)
@@ -159,7 +160,7 @@ def nlevels(n: int, nd: int) -> int:
 
 def make_opts(theta=0.5, tol=1e-6, p=0, levels=-1, leaf_target=0, kernel="log",
               precision="fp64", porder="fixed", timing=False, require_model=False,
-              list_cap=0, swap=False) -> Opts:
+              list_cap=0, swap=False, mutual=False) -> Opts:
     o = Opts()
     load().fmm2d_default_opts(ctypes.byref(o))
     o.theta = float(theta)
@@ -171,7 +172,7 @@ def make_opts(theta=0.5, tol=1e-6, p=0, levels=-1, leaf_target=0, kernel="log",
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.porder = PORDER[porder] if isinstance(porder, str) else int(porder)
     o.flags = ((FLAG_TIMING if timing else 0) | (FLAG_REQUIRE_MODEL if require_model else 0)
-               | (FLAG_LEAF_SWAP if swap else 0))
+               | (FLAG_LEAF_SWAP if swap else 0) | (FLAG_MUTUAL if mutual else 0))
     o.list_cap = int(list_cap)
     return o
 
