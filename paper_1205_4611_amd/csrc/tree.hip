@@ -5,15 +5,22 @@
 //
 // Design (replaces the paper's warp-32 pivot search, Alg. "Partitioning with
 // successive splits", which is non-deterministic across blocks):
-//  * each point set is kept as three index lists per segment: sorted by
-//    (x, index), sorted by (y, index), and in index order.  A stable LSD radix
-//    sort of the order-preserving 64-bit key of each coordinate builds the
-//    first two once.
-//  * one split of every segment is then data-parallel: the median is the
-//    element at rank floor(n/2) of the axis list, and every list is stably
-//    partitioned by the resulting side flag (one scan per list).  Stable
-//    partitions keep each list sorted inside every segment, so the rectangles
-//    of the next step come from the segment ends.
+//  * a stable LSD radix sort of the order-preserving 64-bit key of each
+//    coordinate (ties by index) gives every point its rank in the global
+//    (x, index) and (y, index) orders; comparisons of ranks are exactly the
+//    (coordinate, index) comparisons.
+//  * each source set is then kept as two lists of 8-byte rank records
+//    (rx, ry), one in x order and one in y order inside every segment.  One
+//    split of every segment is data-parallel: the median is the record at
+//    position floor(n/2) of the list of the split axis, which stays as it is
+//    (its first floor(n/2) records are the lo side); only the other list is
+//    stably partitioned by the side flag.  Both lists stay sorted inside every
+//    segment, so the rectangles of the next step come from the segment ends
+//    (coordinates are read from the sorted coordinate arrays at those ranks).
+//  * the last splits of every segment of at most 2048 sources run in one
+//    workgroup in LDS (k_subtree), which also writes the leaf order and the
+//    leaf-ordered sources.  Targets (evaluation away from the sources) follow
+//    the source splits by one pass per step (k_part_lb, decoupled look-back).
 //  * the tree is a pyramid with children 4b..4b+3, so segment j of split step
 //    k becomes segments 2j, 2j+1 of step k+1 and no host round-trip is needed.
 #pragma clang fp contract(off)
