@@ -113,14 +113,16 @@ __device__ __forceinline__ double box_den(const double *__restrict__ n1, const i
     const int lane = threadIdx.x & (WAVE - 1);
     double den = 0.0;
     for (int32_t e = e0 + lane; e < e1; e += 8 * WAVE) {
+        // all index loads, then all value loads (clamped, always valid), then
+        // the sum with the entries past e1 as exact zeros
+        int32_t ix[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ix[u] = widx[min(e + u * WAVE, e1 - 1)];
         double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int32_t eu = e + u * WAVE;
-            v[u] = eu < e1 ? n1[bo + min(max(widx[eu], 0), nbl - 1)] : 0.0;
-        }
+        for (int u = 0; u < 8; ++u) v[u] = n1[bo + min(max(ix[u], 0), nbl - 1)];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) den += v[u];
+        for (int u = 0; u < 8; ++u) den += e + u * WAVE < e1 ? v[u] : 0.0;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) den += __shfl_xor(den, o, WAVE);
@@ -183,13 +185,17 @@ __device__ __forceinline__ float mlp_eval(const float *__restrict__ w, const flo
     return y;
 }
 
+// Every feature inside the training range [lo, hi] (a NaN is outside).  The
+// tests are combined without short-circuit, so that the check is
+// straight-line code after all features are formed (a chain of && compiles
+// to one branch and one LDS round trip per bound).
 __device__ __forceinline__ bool in_range(const float *__restrict__ w, const float f[FMM_NF])
 {
     const float *lo = w + FMM2D_PORDER_NPARAM + 2 * FMM_NF, *hi = lo + FMM_NF;
-    bool ok = true;
+    uint32_t ok = 1u;
 #pragma unroll
-    for (int i = 0; i < FMM_NF; ++i) ok = ok && f[i] >= lo[i] && f[i] <= hi[i];
-    return ok;
+    for (int i = 0; i < FMM_NF; ++i) ok &= (uint32_t)(f[i] >= lo[i]) & (uint32_t)(f[i] <= hi[i]);
+    return ok != 0u;
 }
 
 // Features of every weak pair, in weak-list order: feat[e][8].
