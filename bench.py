@@ -275,7 +275,7 @@ def db_summary(paths, counters: bool):
             disp[(k, g)][d] = du
         for key in sorted(agg, key=lambda kk: -sum(disp[kk].values())):
             n = len(disp[key])
-            vals = " ".join("%s=%.4g" % (cn, v / n) for cn, v in sorted(agg[key].items()))
+            vals = " ".join("%s=%.7g" % (cn, v / n) for cn, v in sorted(agg[key].items()))
             print("%-60s grid=%-9d n=%-3d avg_us=%-9.1f %s" % (key[0][:60], key[1], n,
                                                                  sum(disp[key].values()) / n / 1e3, vals))
 
