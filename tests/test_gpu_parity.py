@@ -235,6 +235,41 @@ def test_l0_is_direct(fmm, orc):
     assert nrm(host(gd), rd) < 1e-13 and nrm(host(gp), rp) < 1e-13
 
 
+def test_log_pairs_wide_range(fmm, orc):
+    """The logarithm and the argument of the LOG kernel's near-field pairs
+    over separations from 1 down to 1e-12, every octant, pairs on an axis
+    (a zero difference of y: the principal branch puts +pi on the negative
+    axis), pairs on the diagonal (|dx| = |dy|) and a geometric approach to one
+    point: at L = 0 every pair is a P2P pair, so Phi and Phi' are compared
+    with the oracle's direct sum, and every target's error with the sum of
+    the sizes of its terms."""
+    rng = np.random.default_rng(191)
+    pts = [rng.uniform(0.0, 1.0, 500) + 1j * rng.uniform(0.0, 1.0, 500),   # every octant
+           rng.uniform(0.1, 0.9, 300) + 0.5j,                                # dy = 0 pairs
+           (lambda t: t + 1j * t)(rng.uniform(0.1, 0.9, 300)),               # |dx| = |dy|
+           0.3 + 0.7j + 1e-12 * (rng.normal(size=300) + 1j * rng.normal(size=300)),
+           0.6 + 0.2j + 10.0 ** (-np.arange(120) / 10.0) * np.exp(1j * rng.uniform(-np.pi, np.pi, 120))]
+    src = np.concatenate(pts)
+    n = len(src)
+    m = workloads.strengths(n, 192)
+    gp, gd = fmm.eval(dev(src), dev(m), p=5, levels=0, kernel="log")
+    rp, rd = orc.direct(src, m)
+    gp, gd = host(gp), host(gd)
+    # the size of every target's terms: sum_j |m_j| (|Log(y - x_j)| + 1 / |y - x_j|)
+    scale = np.zeros(n)
+    for i0 in range(0, n, 256):
+        w = src[i0:i0 + 256, None] - src[None, :]
+        ok = w != 0
+        lw = np.where(ok, np.log(np.where(ok, w, 1.0)), 0.0)
+        iw = np.where(ok, 1.0 / np.where(ok, np.abs(w), 1.0), 0.0)
+        scale[i0:i0 + 256] = (np.abs(m)[None, :] * (np.abs(lw) + iw)).sum(axis=1)
+    e_p = np.max(np.abs(gp - rp) / scale)
+    e_d = np.max(np.abs(gd - rd) / scale)
+    print("log pairs: Phi %.2e, Phi' %.2e of the terms' size" % (e_p, e_d))
+    assert e_p < 1e-14 and e_d < 1e-14
+    assert nrm(gp, rp) < 1e-13 and nrm(gd, rd) < 1e-13
+
+
 def test_operating_point_tol(fmm, orc):
     """10,000 uniform sources at the sources, theta 1/2, p = 17: pointwise
     relative error of Phi' about 1e-6 (TOL of Sec. 5.1), Phi against the
