@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(256) k_p2l(const double4 *__restrict__ srcs,
             const int32_t j0 = __builtin_amdgcn_readlane(mj0, q), j1 = __builtin_amdgcn_readlane(mj1, q);
             for (int32_t j = j0 + r; j < j1; j += 16) {
                 const double4 d = srcs[j];
-                const double2 u = cinv(make_double2(d.x - cx, d.y - cy));
+                const double2 u = cinv_fast(make_double2(d.x - cx, d.y - cy));
                 double2 pw = cmul(make_double2(d.z, d.w), group_power(cpow_ct<KG>(u), g));
                 if (!LOG) pw = cmul(pw, u);
 #pragma unroll
