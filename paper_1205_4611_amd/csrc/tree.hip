@@ -514,6 +514,7 @@ __global__ void k_trec_init(const double *__restrict__ pts, const int32_t *__res
 #define LB_I 16
 #define LB_B (LB_T * LB_I)
 static_assert(LB_B == FMM_LB_TILE, "partition tile size");
+static_assert(LB_I * (LB_T / WAVE) == WAVE, "one wave scans the (stripe, wave) counts of a tile");
 
 struct seg_args {
     const src_rec *slx[2], *sly[2]; // source lists (two buffers each)
