@@ -704,7 +704,7 @@ __device__ __forceinline__ bool rec_lo(const lb_batch &pb, int32_t j, const pt_r
 template <typename R>
 __global__ void __launch_bounds__(LB_T) k_part_lb(lb_batch pb)
 {
-    const lb_list &p = pb.l[blockIdx.y];
+    const lb_list p = blockIdx.y ? pb.l[1] : pb.l[0]; // (a select keeps the fields in scalar registers)
     __shared__ int32_t s_tile, s_carry;
     __shared__ int32_t wc[LB_I * (LB_T / WAVE)]; // lo count per (stripe, wave), then its exclusive scan
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
@@ -827,7 +827,9 @@ template <bool COUNT>
 __global__ void __launch_bounds__(LB_T) k_part_src(ps_batch pb)
 {
     const int q = blockIdx.y; // 0: x list, 1: y list
-    const ps_list &p = pb.l[q];
+    // the list's fields chosen by a select (not an index into the argument
+    // struct), so that they stay in scalar registers
+    const ps_list p = q ? pb.l[1] : pb.l[0];
     __shared__ int32_t wc[LB_I * (LB_T / WAVE)];
     // the segments j0, j0 + 1, ... that meet the tile: start, the record data
     // of their split (pivot rank, axis, buffer bit) and placement (LO, nlo)
@@ -874,39 +876,50 @@ __global__ void __launch_bounds__(LB_T) k_part_src(ps_batch pb)
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
     src_rec r[LB_I];
     uint64_t mk[LB_I];
-    int32_t sg[LB_I]; // window slot of a moving record (or the segment, outside the window), -1 otherwise
+    int32_t sg[LB_I]; // 2 x (window slot, or segment outside the window) + buffer bit of a moving record, else -1
+    // three passes, so that the record loads are all in flight together: the
+    // segment (window slot, or segment outside the window) and buffer of every
+    // moving record, encoded 2 slot + bit (-1: the record stays or is past n);
+    // the loads; the sides
+    if (inwin) {
 #pragma unroll
-    for (int i = 0; i < LB_I; ++i) {
-        const int64_t pos = base + (int64_t)i * LB_T;
-        bool lo = false;
-        sg[i] = -1;
-        if (pos < pb.n) {
-            if (inwin) {
+        for (int i = 0; i < LB_I; ++i) {
+            const int64_t pos = base + (int64_t)i * LB_T;
+            sg[i] = -1;
+            if (pos < pb.n) {
                 int32_t a0 = 0, a1 = nw - 1; // the last window entry <= pos
                 while (a0 < a1) {
                     const int32_t mid = (a0 + a1 + 1) >> 1;
                     if (win[mid] <= pos) a0 = mid; else a1 = mid - 1;
                 }
-                const int ax = wax[a0];
-                if (ax != q) { // this list moves in the segment
-                    sg[i] = a0;
-                    r[i] = ((wbit[a0] & 1) ? p.buf1 : p.buf0)[pos];
-                    lo = (ax ? r[i].ry : r[i].rx) < wpi[a0];
-                }
-            } else {
+                if (wax[a0] != q) sg[i] = 2 * a0 + (wbit[a0] & 1); // this list moves in the segment
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < LB_I; ++i) {
+            const int64_t pos = base + (int64_t)i * LB_T;
+            sg[i] = -1;
+            if (pos < pb.n) {
                 int32_t a0 = j0, a1 = pb.nseg - 1;
                 while (a0 < a1) {
                     const int32_t mid = (a0 + a1 + 1) >> 1;
                     if (pb.start[mid] <= pos) a0 = mid; else a1 = mid - 1;
                 }
-                const int32_t j = a0;
-                const int ax = pb.axis[j];
-                if (ax != q) {
-                    sg[i] = j;
-                    r[i] = ((p.bit[j] & 1) ? p.buf1 : p.buf0)[pos];
-                    lo = (ax ? r[i].ry : r[i].rx) < pb.pi[j];
-                }
+                if (pb.axis[a0] != q) sg[i] = 2 * a0 + (p.bit[a0] & 1);
             }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < LB_I; ++i)
+        if (sg[i] >= 0) r[i] = ((sg[i] & 1) ? p.buf1 : p.buf0)[base + (int64_t)i * LB_T];
+#pragma unroll
+    for (int i = 0; i < LB_I; ++i) {
+        bool lo = false;
+        if (sg[i] >= 0) {
+            const int32_t j = sg[i] >> 1;
+            const int ax = inwin ? wax[j] : pb.axis[j];
+            lo = (ax ? r[i].ry : r[i].rx) < (inwin ? wpi[j] : pb.pi[j]);
         }
         mk[i] = __ballot(lo);
         if (lane == 0) wc[i * (LB_T / WAVE) + w] = __popcll(mk[i]);
@@ -935,12 +948,12 @@ __global__ void __launch_bounds__(LB_T) k_part_src(ps_batch pb)
     for (int i = 0; i < LB_I; ++i) {
         if (sg[i] < 0) continue;
         const int64_t pos = base + (int64_t)i * LB_T;
-        const int32_t j = sg[i];
+        const int32_t j = sg[i] >> 1;
         const bool lo = (mk[i] >> lane) & 1;
         const int32_t before = carry + wc[i * (LB_T / WAVE) + w] + __popcll(mk[i] & lt);
         const int32_t st = inwin ? win[j] : pb.start[j];
         const int32_t LOj = inwin ? wlo[j] : p.LO[j], nlj = inwin ? wnl[j] : pb.nlo[j];
-        const uint8_t bj = inwin ? wbit[j] : p.bit[j];
+        const uint8_t bj = (uint8_t)(sg[i] & 1);
         const int32_t rank = before - LOj; // lo records before pos in the segment
         int64_t dst = lo ? (int64_t)st + rank : (int64_t)st + nlj + (pos - st - rank);
         dst = dst < 0 ? 0 : (dst >= pb.n ? pb.n - 1 : dst); // never leave the array
