@@ -695,12 +695,6 @@ struct lb_batch {
     int32_t *status;
 };
 
-// Side of a target record: lo iff its coordinate is below the pivot coordinate.
-__device__ __forceinline__ bool rec_lo(const lb_batch &pb, int32_t j, const pt_rec &r)
-{
-    return (pb.axis[j] ? r.y : r.x) < pb.pc[j];
-}
-
 template <typename R>
 __global__ void __launch_bounds__(LB_T) k_part_lb(lb_batch pb)
 {
@@ -719,16 +713,25 @@ __global__ void __launch_bounds__(LB_T) k_part_lb(lb_batch pb)
     R r[LB_I];
     uint64_t mk[LB_I];
     int32_t sg[LB_I];
+    // three passes, so that the loads of a pass are in flight together: the
+    // records, then the axis and pivot coordinate of their segments, then the
+    // sides
+#pragma unroll
+    for (int i = 0; i < LB_I; ++i) r[i] = in[min(base + (int64_t)i * LB_T, p.n - 1)]; // (no branch: a valid index)
+    uint8_t ax[LB_I];
+    double pcv[LB_I];
 #pragma unroll
     for (int i = 0; i < LB_I; ++i) {
         const int64_t pos = base + (int64_t)i * LB_T;
-        bool lo = false;
-        sg[i] = -1;
-        if (pos < p.n) {
-            r[i] = in[pos];
-            sg[i] = min(max(r[i].seg, 0), p.nseg - 1);
-            lo = rec_lo(pb, sg[i], r[i]);
-        }
+        const int32_t j = min(max(r[i].seg, 0), p.nseg - 1);
+        sg[i] = pos < p.n ? j : -1;
+        ax[i] = pb.axis[j];
+        pcv[i] = pb.pc[j];
+    }
+#pragma unroll
+    for (int i = 0; i < LB_I; ++i) {
+        // lo iff the record's coordinate on its segment's axis is below the pivot coordinate
+        const bool lo = sg[i] >= 0 && (ax[i] ? r[i].y : r[i].x) < pcv[i];
         mk[i] = __ballot(lo);
         if (lane == 0) wc[i * (LB_T / WAVE) + w] = __popcll(mk[i]);
     }
