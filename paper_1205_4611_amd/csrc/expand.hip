@@ -486,8 +486,13 @@ struct m2l_chunk16 {
     bool valid;
 };
 
+// In two steps, so that no load of a chunk waits for another: m2l_issue16
+// issues every load (all coefficients up to p at a clamped index, the pair's
+// order); m2l_finish16 takes the orders and zeroes the terms above each
+// pair's order.  (Loading the next chunk during the current one's
+// contraction cost a wave per SIMD and was slower.)
 template <int KS, bool LOG>
-__device__ __forceinline__ void m2l_fetch16(const m2l_args &a, int64_t bo, int32_t nbl, int32_t e, int32_t e1,
+__device__ __forceinline__ void m2l_issue16(const m2l_args &a, int64_t bo, int32_t nbl, int32_t e, int32_t e1,
                                             int32_t sbraw, int pr, int kq, m2l_chunk16<KS> &c)
 {
     const int p = a.p, P1 = p + 1;
@@ -496,20 +501,22 @@ __device__ __forceinline__ void m2l_fetch16(const m2l_args &a, int64_t bo, int32
     const int32_t sb = min(max(c.valid ? sbraw : 0, 0), nbl - 1);
     const int64_t gS = bo + sb;
     c.cS = make_double2(a.centre[2 * gS], a.centre[2 * gS + 1]);
-    c.q = c.valid ? p : -1;
-    c.qc = p;
-    if (a.sp) {
-        c.q = c.valid ? (int)a.sp[pe] : -1;
-        // the chunk's largest order bounds its k-steps and row tiles
-        c.qc = __builtin_amdgcn_readfirstlane(max16_i(c.q));
-    }
+    c.q = (a.sp && c.valid) ? (int)a.sp[pe] : p; // (the raw order; finished below)
     const double2 *As = a.A + gS * P1;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int kk = 4 * ks + kq + 1;
-        c.ak[ks] = (kk <= c.q) ? As[kk] : make_double2(0.0, 0.0);
-    }
-    c.a0 = (LOG && c.valid) ? As[0] : make_double2(0.0, 0.0);
+    for (int ks = 0; ks < KS; ++ks) c.ak[ks] = As[min(4 * ks + kq + 1, p)];
+    c.a0 = LOG ? As[0] : make_double2(0.0, 0.0);
+}
+template <int KS, bool LOG>
+__device__ __forceinline__ void m2l_finish16(const m2l_args &a, int kq, m2l_chunk16<KS> &c)
+{
+    c.q = c.valid ? c.q : -1;
+    // the chunk's largest order bounds its k-steps and row tiles
+    c.qc = a.sp ? __builtin_amdgcn_readfirstlane(max16_i(c.q)) : a.p;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+        if (4 * ks + kq + 1 > c.q) c.ak[ks] = make_double2(0.0, 0.0);
+    if (!c.valid) c.a0 = make_double2(0.0, 0.0);
 }
 
 // One chunk of 16 weak pairs in FP64 with MTN row tiles and KSN k-steps
@@ -647,9 +654,10 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, const double *Sop, 
         int32_t sb0 = (e + pr < e1) ? wl[e + pr] : 0;
         for (; e < e1; e += step) {
             m2l_chunk16<KS> cur;
-            m2l_fetch16<KS, LOG>(a, bo, nbl, e, e1, sb0, pr, kq, cur);
+            m2l_issue16<KS, LOG>(a, bo, nbl, e, e1, sb0, pr, kq, cur);
             sb0 = sb1;
             sb1 = (e + 2 * step + pr < e1) ? wl[e + 2 * step + pr] : 0;
+            m2l_finish16<KS, LOG>(a, kq, cur);
             const int ksn = min(max((cur.qc + 3) >> 2, 1), KS), mtn = min((cur.qc >> 4) + 1, MT);
             m2l64_pick<MT, KS, LOG, MT, KS>(mtn, ksn, Sl, Il, cur, cT, kq, re, im);
         }
