@@ -280,6 +280,71 @@ def db_summary(paths, counters: bool):
                                                                  sum(disp[key].values()) / n / 1e3, vals))
 
 
+# kernels of the derived counter table: (name prefix, grid or 0 for any, label)
+COUNTER_TABLE = [
+    ("void k_near<false, false, 20>", 8454144, "k_near (near field, one-stream full launch)"),
+    ("void k_m2l64<2, 5, false>", 0, "k_m2l64 (M2L, FP64 MFMA; fixed and learned orders averaged)"),
+    ("k_porder", 0, "k_porder (features, MLP, sort by order class)"),
+    ("k_subtree", 0, "k_subtree (last splits in LDS, leaf order)"),
+    ("k_rs_scatter", 0, "k_rs_scatter (presort pass, one axis)"),
+    ("k_rs_hist", 0, "k_rs_hist (presort digit histogram, one axis)"),
+    ("void k_part_src<false>", 0, "k_part_src place (global split step)"),
+    ("void k_part_src<true>", 0, "k_part_src count (global split step)"),
+    ("k_srec_init", 0, "k_srec_init (rank records)"),
+    ("void k_p2l<20, false>", 0, "k_p2l (P2L of the swapped criterion)"),
+    ("void k_near_final<false, 20>", 0, "k_near_final (L2P, near + far, output)"),
+]
+
+
+def counter_table(paths, fetch_scale: float, write_scale: float):
+    """Derived per-launch columns from several rocprofv3 counter passes over
+    the same command (one database per pass): VALU% = issue slots filled by
+    VALU instructions (4 cycles each, 16 per FP64 transcendental) over
+    1024 SIMDs x duration x 2.4 GHz; MFMA% = SQ_VALU_MFMA_BUSY_CYCLES over the
+    same; wait% = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; HBM bytes =
+    fetch_scale x FETCH_SIZE + write_scale x WRITE_SIZE (KiB)."""
+    import collections
+    import sqlite3
+    cnt = collections.defaultdict(lambda: collections.defaultdict(list))
+    dur = collections.defaultdict(list)
+    for db in paths:
+        c = sqlite3.connect(db)
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        pdur = {}
+        q = "select kernel_name, grid_size, dispatch_id, counter_name, value, duration from counters_collection"
+        for k, g, d, cn, v, du in c.execute(q):
+            per[(k, g, d)][cn] += v
+            pdur[(k, g, d)] = du
+        for (k, g, d), vals in per.items():
+            for cn, v in vals.items():
+                cnt[(k, g)][cn].append(v)
+            dur[(k, g)].append(pdur[(k, g, d)])
+    slot = 1024 * 2.4e9
+    print("%-62s %8s %10s %6s %6s %6s %9s %7s" % ("kernel (launch)", "avg_us", "VALU_inst", "VALU%", "MFMA%",
+                                                   "wait%", "HBM_MB", "TB/s"))
+    for prefix, grid, label in COUNTER_TABLE:
+        keys = [k for k in cnt if k[0].startswith(prefix) and (grid == 0 or k[1] == grid)]
+        if not keys:
+            continue
+        def avg(cn):
+            v = [x for k in keys for x in cnt[k].get(cn, [])]
+            return sum(v) / len(v) if v else float("nan")
+        d = [x for k in keys for x in dur[k]]
+        t = sum(d) / len(d) / 1e9  # s
+        valu = avg("SQ_INSTS_VALU")
+        mfma_i = avg("SQ_INSTS_VALU_MFMA_F64")
+        trans = avg("SQ_INSTS_VALU_TRANS_F64")
+        mfma_i = 0.0 if mfma_i != mfma_i else mfma_i
+        trans = 0.0 if trans != trans else trans
+        valu_pct = 100.0 * ((valu - mfma_i) * 4 + 12 * trans) / (slot * t)
+        mb = avg("SQ_VALU_MFMA_BUSY_CYCLES")
+        mfma_pct = 100.0 * (0.0 if mb != mb else mb) / (slot * t)
+        wait_pct = 100.0 * avg("SQ_WAIT_INST_ANY") / avg("SQ_WAVE_CYCLES")
+        hbm = (fetch_scale * avg("FETCH_SIZE") + write_scale * avg("WRITE_SIZE")) * 1024
+        print("%-62s %8.1f %10.3g %6.1f %6.1f %6.1f %9.1f %7.2f" % (label, t * 1e6, valu, valu_pct, mfma_pct,
+                                                                    wait_pct, hbm / 1e6, hbm / t / 1e12))
+
+
 def copy_calibration(nbytes: int, reps: int):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -308,11 +373,18 @@ def main():
                     help="other measured workloads to report (comma list, empty for none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES bytes (counter calibration)")
+    ap.add_argument("--counter-table", nargs="+", metavar="DB",
+                    help="derived per-launch counter table from the counter passes' databases")
+    ap.add_argument("--fetch-scale", type=float, default=2.0, help="HBM bytes per FETCH_SIZE byte (copy calibration)")
+    ap.add_argument("--write-scale", type=float, default=1.0, help="HBM bytes per WRITE_SIZE byte (copy calibration)")
     ap.add_argument("--kernel-stats", nargs="+", metavar="DB",
                     help="only print per-kernel statistics of rocprofv3 result databases")
     ap.add_argument("--counter-stats", nargs="+", metavar="DB",
                     help="only print per-kernel counter averages of rocprofv3 --pmc result databases")
     args = ap.parse_args()
+    if args.counter_table:
+        counter_table(args.counter_table, args.fetch_scale, args.write_scale)
+        return
     if args.kernel_stats or args.counter_stats:
         db_summary(args.kernel_stats or args.counter_stats, counters=bool(args.counter_stats))
         return
