@@ -237,47 +237,25 @@ __global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t *__restrict__ k
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// Digit totals: block d sums column d of the histogram.
-__global__ void __launch_bounds__(1024) k_rs_coltot(const int32_t *__restrict__ hist, int nblk,
-                                                     int32_t *__restrict__ tot)
+// Column scan of one pass: block d scans column d of the histogram in place,
+// off[d][b] = sum_{b' < b} hist[d][b'] (the position of block b's keys inside
+// digit d's run), and writes the digit's total tot[d]; the scatter adds the
+// digit bases (the exclusive scan of tot) itself.
+__global__ void __launch_bounds__(1024) k_rs_colscan(int32_t *__restrict__ hist, int nblk, int32_t *__restrict__ tot)
 {
     __shared__ int32_t sh[1024 / WAVE];
-    const int32_t *col = hist + (int64_t)blockIdx.x * nblk;
-    int32_t v = 0;
-    for (int k = threadIdx.x; k < nblk; k += blockDim.x) v += col[k];
-    int32_t t;
-    block_excl_scan(v, sh, &t);
-    if (threadIdx.x == 0) tot[blockIdx.x] = t;
-}
-
-// Scatter offsets of one pass: block d scans column d of the histogram and
-// adds the elements of all smaller digits: off[d][b] = sum_{d' < d} tot[d'] +
-// sum_{b' < b} hist[d][b'].
-__global__ void __launch_bounds__(1024) k_rs_offsets(const int32_t *__restrict__ hist, const int32_t *__restrict__ tot,
-                                                      int nblk, int32_t *__restrict__ off)
-{
-    __shared__ int32_t sh[1024 / WAVE];
-    __shared__ int32_t s_base;
     const int d = blockIdx.x;
-    if (threadIdx.x < WAVE) {
-        int32_t v = 0;
-        for (int e = threadIdx.x; e < d; e += WAVE) v += tot[e];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
-        if (threadIdx.x == 0) s_base = v;
-    }
-    __syncthreads();
-    int32_t carry = s_base;
-    const int32_t *col = hist + (int64_t)d * nblk;
-    int32_t *ocol = off + (int64_t)d * nblk;
+    int32_t *col = hist + (int64_t)d * nblk;
+    int32_t carry = 0;
     for (int c0 = 0; c0 < nblk; c0 += blockDim.x) {
         const int k = c0 + threadIdx.x;
         const int32_t v = k < nblk ? col[k] : 0;
         int32_t t;
         const int32_t ex = block_excl_scan(v, sh, &t);
-        if (k < nblk) ocol[k] = carry + ex;
+        if (k < nblk) col[k] = carry + ex;
         carry += t;
     }
+    if (threadIdx.x == 0) tot[d] = carry;
 }
 
 // Scatter of one pass.  Wave w of a block takes the block's elements
@@ -295,7 +273,8 @@ __global__ void __launch_bounds__(RS_T, 4) k_rs_scatter(const uint64_t *__restri
                                                       uint64_t *__restrict__ kout,
                                                       int32_t *__restrict__ vout, int64_t n,
                                                       int shift, const int32_t *__restrict__ off,
-                                                      int nblk, int32_t *__restrict__ rank)
+                                                      const int32_t *__restrict__ tot, int nblk,
+                                                      int32_t *__restrict__ rank)
 {
     constexpr int NW = RS_T / WAVE, PER_W = RS_BLOCK / NW, IT = PER_W / WAVE;
     static_assert(PER_W <= 65535 && RS_BLOCK <= 65535, "per-wave counts and bases are 16-bit");
@@ -363,8 +342,13 @@ __global__ void __launch_bounds__(RS_T, 4) k_rs_scatter(const uint64_t *__restri
     }
     __syncthreads();
     // output base of every digit less its start in the tile: slot j of digit d
-    // goes to position dstart[d] + j
-    dstart[tid] = off[(int64_t)tid * nblk + blockIdx.x] - dstart[tid];
+    // goes to position dstart[d] + j (the digit's base: the exclusive scan of
+    // the totals, thread tid = digit)
+    {
+        int32_t all;
+        const int32_t dbase = block_excl_scan(tot[tid], sh, &all);
+        dstart[tid] = dbase + off[(int64_t)tid * nblk + blockIdx.x] - dstart[tid];
+    }
     __syncthreads();
     const int nvalid = (int)min((int64_t)RS_BLOCK, n - base);
     for (int j = tid; j < nvalid; j += RS_T) {
@@ -404,11 +388,11 @@ static hipError_t radix_sort(int64_t n, int passes, uint64_t *k0, uint64_t *k1, 
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
         k_rs_hist<<<nblk, RS_T, 0, st>>>(ka, n, shift, hist, nblk);
-        k_rs_coltot<<<256, 1024, 0, st>>>(hist, nblk, tot);
-        k_rs_offsets<<<256, 1024, 0, st>>>(hist, tot, nblk, off);
+        k_rs_colscan<<<256, 1024, 0, st>>>(hist, nblk, tot);
         // the last pass writes the values to out (and, given rank, the inverse)
         const bool last = pass == passes - 1;
-        k_rs_scatter<<<nblk, RS_T, 0, st>>>(ka, va, kb, last ? out : vb, n, shift, off, nblk, last ? rank : nullptr);
+        k_rs_scatter<<<nblk, RS_T, 0, st>>>(ka, va, kb, last ? out : vb, n, shift, off, tot, nblk,
+                                            last ? rank : nullptr);
         uint64_t *tk = ka; ka = kb; kb = tk;
         int32_t *tv = va; va = vb; vb = tv;
     }
