@@ -368,7 +368,8 @@ def main():
     ap.add_argument("--cpu-single-sample", type=int, default=1 << 19)
     ap.add_argument("--paths", default="learned,fp64,far32,mixed,mutual")
     ap.add_argument("--phase-steps", type=int, default=5,
-                    help="steps with per-phase events (run in order on one stream) after the timed ones")
+                    help="steps with per-phase events (run in order on one stream) after the timed ones; "
+                         "at least 1, since the roofline's near-field launch time comes from them")
     ap.add_argument("--workloads", default=",".join(e[0] for e in EXTRA),
                     help="other measured workloads to report (comma list, empty for none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -382,6 +383,8 @@ def main():
     ap.add_argument("--counter-stats", nargs="+", metavar="DB",
                     help="only print per-kernel counter averages of rocprofv3 --pmc result databases")
     args = ap.parse_args()
+    if args.phase_steps < 1:
+        ap.error("--phase-steps must be at least 1 (the roofline's near-field launch time is measured in those steps)")
     if args.counter_table:
         counter_table(args.counter_table, args.fetch_scale, args.write_scale)
         return
