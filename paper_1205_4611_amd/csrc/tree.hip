@@ -221,20 +221,31 @@ __global__ void k_rs_init(const double *__restrict__ pts, int64_t n, int axis,
     flag_nonfinite(bad, status);
 }
 
-// Per-block digit histogram of one pass: hist[digit][block].
+// Tile of block b of nb when blocks go to the 8 XCDs in turn (b mod 8): the
+// blocks of one XCD take consecutive tiles, so that the cache lines which
+// neighbouring tiles share (the ends of their digit runs in the scatter, the
+// histogram words of consecutive tiles) are written through one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+// Per-tile digit histogram of one pass: hist[digit][tile].
 __global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t *__restrict__ keys, int64_t n,
                                                    int shift, int32_t *__restrict__ hist, int nblk)
 {
     __shared__ int32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_BLOCK;
+    const int tile = xcd_tile(blockIdx.x, nblk);
+    const int64_t base = (int64_t)tile * RS_BLOCK;
     for (int t = 0; t < RS_TILES; ++t) {
         int64_t k = base + (int64_t)t * RS_T + threadIdx.x;
         if (k < n) atomicAdd(&h[(keys[k] >> shift) & 255], 1);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    hist[(int64_t)threadIdx.x * nblk + tile] = h[threadIdx.x];
 }
 
 // Column scan of one pass: block d scans column d of the histogram in place,
@@ -288,7 +299,8 @@ __global__ void __launch_bounds__(RS_T, 4) k_rs_scatter(const uint64_t *__restri
 #pragma unroll
     for (int q = 0; q < NW; ++q) wc[q][tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_BLOCK;
+    const int tile = xcd_tile(blockIdx.x, nblk);
+    const int64_t base = (int64_t)tile * RS_BLOCK;
     const int64_t wbase = base + (int64_t)w * PER_W;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
     uint64_t key[IT];
@@ -347,7 +359,7 @@ __global__ void __launch_bounds__(RS_T, 4) k_rs_scatter(const uint64_t *__restri
     {
         int32_t all;
         const int32_t dbase = block_excl_scan(tot[tid], sh, &all);
-        dstart[tid] = dbase + off[(int64_t)tid * nblk + blockIdx.x] - dstart[tid];
+        dstart[tid] = dbase + off[(int64_t)tid * nblk + tile] - dstart[tid];
     }
     __syncthreads();
     const int nvalid = (int)min((int64_t)RS_BLOCK, n - base);
