@@ -46,6 +46,16 @@ __device__ __forceinline__ int32_t xcd_order(int32_t b, int32_t b0, int32_t b1)
     return ((i / XCD_RUN) * 8 + x) * XCD_RUN + i % XCD_RUN;
 }
 
+// Tile of block b of nb for work of equal size per tile: the blocks of one
+// XCD (b mod 8) take one range of consecutive tiles, so that the cache lines
+// which neighbouring tiles share (the ends of their output runs) are written
+// through one L2.  A bijection onto [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 __device__ __forceinline__ int32_t wave_index()
 {
     return __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64));

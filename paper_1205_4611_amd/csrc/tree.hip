@@ -221,16 +221,6 @@ __global__ void k_rs_init(const double *__restrict__ pts, int64_t n, int axis,
     flag_nonfinite(bad, status);
 }
 
-// Tile of block b of nb when blocks go to the 8 XCDs in turn (b mod 8): the
-// blocks of one XCD take consecutive tiles, so that the cache lines which
-// neighbouring tiles share (the ends of their digit runs in the scatter, the
-// histogram words of consecutive tiles) are written through one L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb)
-{
-    const int x = b & 7, q = nb >> 3, r = nb & 7;
-    return x * q + min(x, r) + (b >> 3);
-}
-
 // Per-tile digit histogram of one pass: hist[digit][tile].
 __global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t *__restrict__ keys, int64_t n,
                                                    int shift, int32_t *__restrict__ hist, int nblk)
