@@ -994,19 +994,49 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
     const int32_t g0 = blockIdx.x;
     const int32_t base = a.sst[g0];
     const int32_t n = min(max(a.sst[g0 + 1] - base, 0), SUB_S);
-    for (int i = tid; i < n; i += SUB_T) {
-        const src_rec r = a.lx[a.bx[g0] & 1][base + i];
-        const int32_t rmax = (int32_t)a.ns - 1; // ranks index the sorted coordinates
-        rxl[i] = min(max(r.rx, 0), rmax);
-        ryl[i] = min(max(r.ry, 0), rmax);
-        pid[i] = a.px[rxl[i]];
-        lst[0][0][i] = (uint16_t)i;
+    const int32_t rmax = (int32_t)a.ns - 1; // ranks index the sorted coordinates
+    // a thread's records, then their original indices, each set of loads in
+    // flight together; position i = tid + u SUB_T
+    {
+        const src_rec *lx = a.lx[a.bx[g0] & 1] + base;
+        int32_t rx[SUB_I], ry[SUB_I], ox[SUB_I];
+#pragma unroll
+        for (int u = 0; u < SUB_I; ++u) {
+            const int i = tid + u * SUB_T;
+            const src_rec r = i < n ? lx[i] : src_rec{0, 0};
+            rx[u] = min(max(r.rx, 0), rmax);
+            ry[u] = min(max(r.ry, 0), rmax);
+        }
+#pragma unroll
+        for (int u = 0; u < SUB_I; ++u) ox[u] = a.px[rx[u]];
+#pragma unroll
+        for (int u = 0; u < SUB_I; ++u) {
+            const int i = tid + u * SUB_T;
+            if (i < n) {
+                rxl[i] = rx[u];
+                ryl[i] = ry[u];
+                pid[i] = ox[u];
+                lst[0][0][i] = (uint16_t)i;
+            }
+        }
+    }
+    // the y list of the same points, as local ids (its x ranks loaded first)
+    int32_t yrx[SUB_I];
+    {
+        const src_rec *ly = a.ly[a.by[g0] & 1] + base;
+#pragma unroll
+        for (int u = 0; u < SUB_I; ++u) {
+            const int i = tid + u * SUB_T;
+            yrx[u] = i < n ? ly[i].rx : 0;
+        }
     }
     __syncthreads();
-    // the y list of the same points, as local ids
     bool missing = false;
-    for (int i = tid; i < n; i += SUB_T) {
-        const int32_t rx = a.ly[a.by[g0] & 1][base + i].rx;
+#pragma unroll
+    for (int u = 0; u < SUB_I; ++u) {
+        const int i = tid + u * SUB_T;
+        if (i >= n) continue;
+        const int32_t rx = yrx[u];
         int32_t lo_i = 0, hi_i = n - 1;
         while (lo_i < hi_i) {
             const int32_t mid = (lo_i + hi_i) >> 1;
@@ -1058,29 +1088,37 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
         __syncthreads();
         if (!split) break;
         const int nxt = cur ^ 1;
-        // (b) lo flags of both lists, block-wide exclusive scans
+        // (b) lo flags of both lists, block-wide exclusive scans.  The
+        // sub-segment of position p is the last t with st[t] <= p; a thread's
+        // positions are consecutive and both lists share the starts, so one
+        // binary search and forward steps give all of them.
         bool lo[2][SUB_I];
-        int32_t tseg[2][SUB_I];
+        int32_t tseg[SUB_I];
+        {
+            const int p0 = tid * SUB_I;
+            int32_t lo_t = 0, hi_t = nsub - 1;
+            while (lo_t < hi_t) {
+                const int32_t mid = (lo_t + hi_t + 1) >> 1;
+                if (st[cur][mid] <= p0) lo_t = mid; else hi_t = mid - 1;
+            }
+#pragma unroll
+            for (int u = 0; u < SUB_I; ++u) {
+                while (lo_t + 1 < nsub && st[cur][lo_t + 1] <= p0 + u) ++lo_t;
+                tseg[u] = lo_t;
+            }
+        }
         for (int q = 0; q < 2; ++q) {
             int32_t cnt = 0;
 #pragma unroll
             for (int u = 0; u < SUB_I; ++u) {
                 const int p = tid * SUB_I + u;
                 bool f = false;
-                int32_t t = 0;
                 if (p < n) {
-                    // sub-segment of position p: the last t with st[t] <= p
-                    int32_t lo_t = 0, hi_t = nsub - 1;
-                    while (lo_t < hi_t) {
-                        const int32_t mid = (lo_t + hi_t + 1) >> 1;
-                        if (st[cur][mid] <= p) lo_t = mid; else hi_t = mid - 1;
-                    }
-                    t = lo_t;
+                    const int32_t t = tseg[u];
                     const uint16_t id = lst[cur][q][p], pv = piv[t];
                     f = axs[t] ? (ryl[id] < ryl[pv]) : (rxl[id] < rxl[pv]);
                 }
                 lo[q][u] = f;
-                tseg[q][u] = t;
                 cnt += f;
             }
             int32_t tot;
@@ -1099,7 +1137,7 @@ __global__ void __launch_bounds__(SUB_T) k_subtree(subtree_args a)
             for (int u = 0; u < SUB_I; ++u) {
                 const int p = tid * SUB_I + u;
                 if (p < n) {
-                    const int32_t t = tseg[q][u];
+                    const int32_t t = tseg[u];
                     const int32_t s0 = st[cur][t], m = st[cur][t + 1] - s0;
                     const int32_t r = exs[q][p] - exs[q][s0]; // lo positions before p in t
                     const int32_t dst = lo[q][u] ? s0 + r : s0 + m / 2 + (p - s0 - r);
