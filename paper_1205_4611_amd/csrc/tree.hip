@@ -127,28 +127,38 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_down(fmm_scan_jobs J, int64_t n
     }
 }
 
-// Small arrays: one block of 1024 threads per job walks the array in chunks.
+// Small arrays (n <= SCAN_SMALL): one block of 1024 threads per job; thread t
+// takes the SCAN_SMALL / 1024 consecutive elements from SCAN_SMALL/1024 t, all
+// loaded before one block scan of the per-thread sums.
+#define SCAN_SMALL 16384
+#define SCAN_SMALL_I (SCAN_SMALL / 1024)
 __global__ void __launch_bounds__(1024) k_scan_single(fmm_scan_jobs J, int64_t n)
 {
     __shared__ int32_t sh[1024 / WAVE];
     const int32_t *__restrict__ in = J.in[blockIdx.y];
     int32_t *__restrict__ out = J.out[blockIdx.y];
-    int32_t carry = J.base[blockIdx.y] ? *J.base[blockIdx.y] : 0;
-    for (int64_t c = 0; c < n; c += blockDim.x) {
-        const int64_t k = c + threadIdx.x;
-        const int32_t v = k < n ? in[k] : 0;
-        int32_t tot;
-        const int32_t ex = block_excl_scan(v, sh, &tot);
-        if (k < n) out[k] = carry + ex;
-        carry += tot;
+    const int32_t base = J.base[blockIdx.y] ? *J.base[blockIdx.y] : 0;
+    const int64_t k0 = (int64_t)threadIdx.x * SCAN_SMALL_I;
+    int32_t v[SCAN_SMALL_I];
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_SMALL_I; ++i) v[i] = k0 + i < n ? in[k0 + i] : 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_SMALL_I; ++i) s += v[i];
+    int32_t tot;
+    int32_t run = base + block_excl_scan(s, sh, &tot);
+#pragma unroll
+    for (int i = 0; i < SCAN_SMALL_I; ++i) {
+        if (k0 + i < n) out[k0 + i] = run;
+        run += v[i];
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    if (threadIdx.x == 0) out[n] = base + tot;
 }
 
 hipError_t fmm_scan_i32_jobs(const fmm_scan_jobs &J, int njobs, int64_t n, hipStream_t st)
 {
     if (njobs < 1 || njobs > FMM_SCAN_JOBS) return hipErrorInvalidValue;
-    if (n <= 16384) {
+    if (n <= SCAN_SMALL) {
         k_scan_single<<<dim3(1, njobs), 1024, 0, st>>>(J, n);
         return hipGetLastError();
     }
