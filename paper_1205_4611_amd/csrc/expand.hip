@@ -401,8 +401,8 @@ __device__ __forceinline__ double2 clog_principal(double2 z)
 }
 
 #define M2L_HEAVY FMM_M2L_HEAVY // boxes with more weak pairs are cut into segments
-#define M2L_SEG FMM_M2L_SEG     // pairs per segment (one 8-wave workgroup each)
-#define M2L_WAVES 8
+#define M2L_SEG FMM_M2L_SEG     // pairs per segment (one workgroup each)
+#define M2L_WAVES 4
 
 __device__ __forceinline__ int32_t m2l_range(const m2l_args &a, int64_t g, int &l, int32_t &e0, int32_t &e1)
 {
@@ -672,11 +672,23 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, const double *Sop, 
         }
 }
 
+// Waves per SIMD the register budget is sized for: three where the body fits
+// in 168 VGPRs without spills (row tiles and k-steps of p <= 20, harmonic
+// kernel), two (256 VGPRs) otherwise.  Workgroups are M2L_WAVES = 4 waves,
+// one per SIMD, so that the groups resident on a CU reach that number (with
+// 8-wave groups, 2 waves per SIMD each, a CU held one group at 168 VGPRs).
+template <int MT, int KS, bool LOG>
+constexpr int m2l_waves_per_simd()
+{
+    return (MT <= 2 && KS <= 5 && !LOG) ? 3 : 2;
+}
+
 // One launch: blocks [0, H) take the boxes with more than M2L_HEAVY weak pairs
 // (M2L_WAVES waves per box, fixed-order LDS reduction); the other blocks take
 // the light boxes, one wave per box.
 template <int MT, int KS, bool LOG>
-__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l64(m2l_args a, int32_t H)
+__global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_simd<MT, KS, LOG>())))
+k_m2l64(m2l_args a, int32_t H)
 {
     __shared__ double part[M2L_WAVES][MT * 16][2];
     // S_{l,k} = C(l + k, l) for rows l < 16 MT, k < 4 KS (zero beyond p, and
@@ -901,7 +913,7 @@ __device__ __forceinline__ double m2l32_unscale(double v, int row, double isT)
 // (M2L_WAVES waves per box, fixed-order LDS reduction); the other blocks take
 // the light boxes, one wave per box.
 template <int MT, int KS, bool LOG>
-__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l32(m2l_args a, int32_t H)
+__global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_per_eu(2))) k_m2l32(m2l_args a, int32_t H)
 {
     __shared__ double part[M2L_WAVES][MT * 16][2];
     const int lane = threadIdx.x & (WAVE - 1);
