@@ -478,8 +478,8 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
         HIPCHK(h, hipEventRecord(h->sev[5], sb));
         // The near field needs only the lists and the leaf multipoles (M2P).
         // Its heavy-leaf units run beside the order phase; its light leaves
-        // wait for M2L: M2L waves hold 160 VGPRs and find little room once
-        // the near kernel's 48-VGPR waves fill the CUs, so side by side M2L
+        // wait for M2L: M2L waves hold 168 VGPRs and find little room once
+        // the near kernel's 49-VGPR waves fill the CUs, so side by side M2L
         // ran past the end of the near kernel; alone it runs at full rate,
         // and L2L and P2L run beside the light leaves.
         HIPCHK(h, hipStreamWaitEvent(st, h->sev[6], 0));
