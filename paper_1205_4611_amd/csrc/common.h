@@ -162,6 +162,7 @@ struct fmm_eval_args {
     int porder;                   // per-pair orders (sorted lists sw/sp) in use
     int mutual;                   // mutual near field (at the sources, harmonic, FP64, leaves <= 64)
     int32_t *status;
+    unsigned upward_blocks;       // grid cap of P2M and M2M (0: none)
 };
 hipError_t fmm_p2m(const fmm_eval_args &a, hipStream_t st);
 hipError_t fmm_m2m(const fmm_eval_args &a, hipStream_t st);

@@ -157,7 +157,8 @@ __device__ __forceinline__ double2 group_power(double2 zK, int g)
 }
 
 // ------------------------------------------------------------------ P2M --
-// One wave per leaf: s_k = sum m (x-c)^k, then
+// One wave per leaf (a wave takes leaves w, w + waves of the grid, ...): s_k =
+// sum m (x-c)^k, then
 //   LOG:      a_0 = s_0, a_k = -s_k / k
 //   HARMONIC: a_0 = 0,   a_k = s_{k-1}
 template <int PM>
@@ -170,35 +171,36 @@ __global__ void __launch_bounds__(256) k_p2m(const double4 *__restrict__ srcs,
     constexpr int KG = p2_groups<PM>::KG;
     const int lane = threadIdx.x & (WAVE - 1);
     const int r = lane & 15, g = lane >> 4, kb = KG * g;
-    const int32_t b = wave_index();
-    if (b >= nleaf) return;
-    const int32_t s0 = sst[b], s1 = sst[b + 1];
-    const double cx = centre[2 * (int64_t)b], cy = centre[2 * (int64_t)b + 1];
-    double sr[KG], si[KG];
+    const int32_t nwv = (int32_t)(gridDim.x * (blockDim.x / WAVE));
+    for (int32_t b = wave_index(); b < nleaf; b += nwv) {
+        const int32_t s0 = sst[b], s1 = sst[b + 1];
+        const double cx = centre[2 * (int64_t)b], cy = centre[2 * (int64_t)b + 1];
+        double sr[KG], si[KG];
 #pragma unroll
-    for (int t = 0; t < KG; ++t) { sr[t] = 0.0; si[t] = 0.0; }
-    for (int32_t j = s0 + r; j < s1; j += 16) {
-        const double4 d = srcs[j];
-        const double2 w = make_double2(d.x - cx, d.y - cy);
-        double2 pw = cmul(make_double2(d.z, d.w), group_power(cpow_ct<KG>(w), g));
+        for (int t = 0; t < KG; ++t) { sr[t] = 0.0; si[t] = 0.0; }
+        for (int32_t j = s0 + r; j < s1; j += 16) {
+            const double4 d = srcs[j];
+            const double2 w = make_double2(d.x - cx, d.y - cy);
+            double2 pw = cmul(make_double2(d.z, d.w), group_power(cpow_ct<KG>(w), g));
+#pragma unroll
+            for (int t = 0; t < KG; ++t) {
+                sr[t] += pw.x;
+                si[t] += pw.y;
+                if (t + 1 < KG) pw = cmul(pw, w);
+            }
+        }
+        double2 *out = A + (int64_t)b * (p + 1);
 #pragma unroll
         for (int t = 0; t < KG; ++t) {
-            sr[t] += pw.x;
-            si[t] += pw.y;
-            if (t + 1 < KG) pw = cmul(pw, w);
-        }
-    }
-    double2 *out = A + (int64_t)b * (p + 1);
-#pragma unroll
-    for (int t = 0; t < KG; ++t) {
-        const double re = sum16_64(sr[t]), im = sum16_64(si[t]);
-        const int k = kb + t;
-        if (r == 0 && k <= p) {
-            if (kernel == FMM2D_KERNEL_LOG) {
-                out[k] = (k == 0) ? make_double2(re, im) : make_double2(-re / k, -im / k);
-            } else {
-                if (k < p) out[k + 1] = make_double2(re, im);
-                if (k == 0) out[0] = make_double2(0.0, 0.0);
+            const double re = sum16_64(sr[t]), im = sum16_64(si[t]);
+            const int k = kb + t;
+            if (r == 0 && k <= p) {
+                if (kernel == FMM2D_KERNEL_LOG) {
+                    out[k] = (k == 0) ? make_double2(re, im) : make_double2(-re / k, -im / k);
+                } else {
+                    if (k < p) out[k + 1] = make_double2(re, im);
+                    if (k == 0) out[0] = make_double2(0.0, 0.0);
+                }
             }
         }
     }
@@ -297,44 +299,46 @@ __global__ void __launch_bounds__(256) k_p2l(const double4 *__restrict__ srcs,
 }
 
 // ------------------------------------------------------------------ M2M --
-// Thread per (parent, coefficient l): a'_l = sum over the 4 children of
-// -a_0 r^l / l + sum_{k=1..l} C(l-1,k-1) a_k r^{l-k},  r = c_child - c_parent.
+// Thread per (parent, coefficient l), grid-stride: a'_l = sum over the 4
+// children of -a_0 r^l / l + sum_{k=1..l} C(l-1,k-1) a_k r^{l-k},
+// r = c_child - c_parent.
 __global__ void k_m2m(const double *__restrict__ centre, double2 *__restrict__ A,
                       const double *__restrict__ binom, int p, int l, int64_t nbl)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int P1 = p + 1;
-    if (t >= nbl * P1) return;
-    const int64_t b = t / P1;
-    const int lc = (int)(t - b * P1);
-    const int64_t g = d_box_off(l) + b;
-    const double2 cp = make_double2(centre[2 * g], centre[2 * g + 1]);
-    double2 acc = make_double2(0.0, 0.0);
-    for (int q = 0; q < 4; ++q) {
-        const int64_t c = d_box_off(l + 1) + 4 * b + q;
-        const double2 r = make_double2(centre[2 * c] - cp.x, centre[2 * c + 1] - cp.y);
-        const double2 *a = A + c * P1;
-        if (lc == 0) {
-            acc.x += a[0].x;
-            acc.y += a[0].y;
-        } else {
-            double2 s = make_double2(0.0, 0.0), pw = make_double2(1.0, 0.0);
-            for (int k = lc; k >= 1; --k) {
-                const double cb = binom[(lc - 1) * FMM_BN + (k - 1)];
-                const double2 ak = a[k];
-                const double2 tk = cmul(ak, pw);
-                s.x += cb * tk.x;
-                s.y += cb * tk.y;
-                pw = cmul(pw, r);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nbl * P1;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t / P1;
+        const int lc = (int)(t - b * P1);
+        const int64_t g = d_box_off(l) + b;
+        const double2 cp = make_double2(centre[2 * g], centre[2 * g + 1]);
+        double2 acc = make_double2(0.0, 0.0);
+        for (int q = 0; q < 4; ++q) {
+            const int64_t c = d_box_off(l + 1) + 4 * b + q;
+            const double2 r = make_double2(centre[2 * c] - cp.x, centre[2 * c + 1] - cp.y);
+            const double2 *a = A + c * P1;
+            if (lc == 0) {
+                acc.x += a[0].x;
+                acc.y += a[0].y;
+            } else {
+                double2 s = make_double2(0.0, 0.0), pw = make_double2(1.0, 0.0);
+                for (int k = lc; k >= 1; --k) {
+                    const double cb = binom[(lc - 1) * FMM_BN + (k - 1)];
+                    const double2 ak = a[k];
+                    const double2 tk = cmul(ak, pw);
+                    s.x += cb * tk.x;
+                    s.y += cb * tk.y;
+                    pw = cmul(pw, r);
+                }
+                const double2 a0 = cmul(a[0], pw); // a_0 r^l
+                s.x -= a0.x / lc;
+                s.y -= a0.y / lc;
+                acc.x += s.x;
+                acc.y += s.y;
             }
-            const double2 a0 = cmul(a[0], pw); // a_0 r^l
-            s.x -= a0.x / lc;
-            s.y -= a0.y / lc;
-            acc.x += s.x;
-            acc.y += s.y;
         }
+        A[g * P1 + lc] = acc;
     }
-    A[g * P1 + lc] = acc;
 }
 
 // ------------------------------------------------------------------ L2L --
@@ -1037,7 +1041,8 @@ static void launch_p2m(const fmm_eval_args &a, hipStream_t st)
 {
     const fmm_layout &lay = *a.lay;
     const int64_t nleaf = nbox(a.L);
-    const unsigned nblk = (unsigned)((nleaf + 3) / 4);
+    unsigned nblk = (unsigned)((nleaf + 3) / 4);
+    if (a.upward_blocks && nblk > a.upward_blocks) nblk = a.upward_blocks;
     k_p2m<PM><<<nblk, 256, 0, st>>>(WSC(double4, lay.srcs),
                                     WSC(int32_t, lay.sstart) + start_off(a.L),
                                     WSC(double, lay.centre) + 2 * box_off(a.L),
@@ -1082,7 +1087,9 @@ hipError_t fmm_m2m(const fmm_eval_args &a, hipStream_t st)
     const fmm_layout &lay = *a.lay;
     for (int l = a.L - 1; l >= 0; --l) {
         const int64_t nt = nbox(l) * (a.p + 1);
-        k_m2m<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(WSC(double, lay.centre), WSC(double2, lay.A),
+        unsigned nblk = (unsigned)((nt + 255) / 256);
+        if (a.upward_blocks && nblk > a.upward_blocks) nblk = a.upward_blocks;
+        k_m2m<<<nblk, 256, 0, st>>>(WSC(double, lay.centre), WSC(double2, lay.A),
                                                             a.binom, a.p, l, nbox(l));
     }
     return hipGetLastError();

@@ -32,6 +32,7 @@ struct fmm2d_handle {
     // multipoles done (6)
     hipStream_t side;
     hipEvent_t sev[7];
+    int n_cu;               // compute units of the device
     int timing_valid;
     hipStream_t last_stream;
     // learned order model (device copy, owned) and caller-given orders (not owned)
@@ -262,6 +263,7 @@ extern "C" int fmm2d_create(fmm2d_handle **out, int device)
     }
     for (int i = 0; i <= FMM2D_NPHASE && e == hipSuccess; ++i) e = hipEventCreate(&h->ev[i]);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, device);
     for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&h->sev[i], hipEventDisableTiming);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) {
@@ -427,6 +429,11 @@ extern "C" int fmm2d_eval(fmm2d_handle *h, int64_t n_src, const double *src, con
     ea.porder = use_model || use_given;
     ea.mutual = mutual;
     ea.status = h->d_status;
+    // Beside the lists, P2M and M2M run on at most 4 workgroups per CU (grid-
+    // stride loops), so that the lists' single-workgroup kernels find room on
+    // the CUs instead of waiting for the upward pass to drain; the upward pass
+    // still ends long before M2L needs it.
+    ea.upward_blocks = fork ? 4u * (unsigned)h->n_cu : 0u;
     fmm_porder_args pa = porder_args(h, w, lay, L, p, cap);
     if (use_model) {
         pa.model = h->d_model;
