@@ -264,8 +264,20 @@ def db_summary(paths, counters: bool):
                 agg[name][1] += du / 1e3
             tot = sum(v[1] for v in agg.values()) or 1.0
             print("%-70s %6s %11s %10s %6s" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
-            for name, (n, us) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+            ranked = sorted(agg.items(), key=lambda kv: -kv[1][1])
+            for name, (n, us) in ranked:
                 print("%-70s %6d %11.3f %10.1f %6.2f" % (name[:70], n, us / 1e3, us / n, 100.0 * us / tot))
+            # the three costliest GPU kernels of the library by launch size (the grid
+            # tells a full near-field launch from its split halves)
+            top = [nm for nm, _ in ranked if nm.startswith(("k_", "void k_")) and "k_direct" not in nm][:3]
+            grid = collections.defaultdict(lambda: [0, 0.0])
+            for name, du, gx in c.execute("select name, duration, grid_x from kernels"):
+                if name in top:
+                    grid[(name, gx)][0] += 1
+                    grid[(name, gx)][1] += du / 1e3
+            print("# by grid size (threads), the three costliest library kernels")
+            for (name, gx), (n, us) in sorted(grid.items(), key=lambda kv: (top.index(kv[0][0]), -kv[1][1])):
+                print("%-60s grid=%-9d %6d %11.3f %10.1f" % (name[:60], gx, n, us / 1e3, us / n))
             continue
         agg = collections.defaultdict(lambda: collections.defaultdict(float))
         disp = collections.defaultdict(dict)
