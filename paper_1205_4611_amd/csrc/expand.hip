@@ -213,7 +213,21 @@ __global__ void __launch_bounds__(256) k_p2m(const double4 *__restrict__ srcs,
 //   LOG:      b_0 += sum m Log(c - x),   b_l -= (sum m u^l) / l   (l >= 1)
 //   HARMONIC: b_l -= sum m u^{l+1}                               (l >= 0)
 // One wave per target leaf; the list entries are read once, up to 64 at a
-// time.  The Log term of the log kernel is summed by all 64 lanes apart.
+// time.  Lane = 32 g + r: source slot r (sources r, r + 32, ...) and the
+// terms k = g, g + 2, ... of parity g, so a lane starts at m u^g (LOG) or
+// m u^(g+1) and steps by u^2; the sum over sources is a reduction over the 32
+// lanes of its half.  The Log term of the log kernel is summed by all 64
+// lanes apart.
+template <int PM>
+struct p2l_terms {
+    static constexpr int KT = (PM + 2) / 2; // terms of parity 0 cover k = 0..PM
+};
+__device__ __forceinline__ double sum32_64(double v)
+{
+    v = sum16_64(v);
+    return v + __shfl_xor(v, 16, WAVE);
+}
+
 template <int PM, bool LOG>
 __global__ void __launch_bounds__(256) k_p2l(const double4 *__restrict__ srcs,
                                               const int32_t *__restrict__ sst,
@@ -222,18 +236,17 @@ __global__ void __launch_bounds__(256) k_p2l(const double4 *__restrict__ srcs,
                                               const double *__restrict__ centre,
                                               double2 *__restrict__ B, int p, int32_t nleaf, int32_t lcap)
 {
-    constexpr int KG = p2_groups<PM>::KG;
+    constexpr int KT = p2l_terms<PM>::KT;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int r = lane & 15, g = lane >> 4, kb = KG * g;
+    const int r = lane & 31, g = lane >> 5;
     const int32_t t = wave_index();
     if (t >= nleaf) return;
     const int32_t e0 = min(poff[t], lcap), e1 = min(poff[t + 1], lcap);
     if (e0 >= e1) return;
     const double cx = centre[2 * (int64_t)t], cy = centre[2 * (int64_t)t + 1];
-    // LOG: the lane's terms start at u^kb; HARMONIC: at u^(kb+1)
-    double sr[KG], si[KG];
+    double sr[KT], si[KT];
 #pragma unroll
-    for (int q = 0; q < KG; ++q) { sr[q] = 0.0; si[q] = 0.0; }
+    for (int q = 0; q < KT; ++q) { sr[q] = 0.0; si[q] = 0.0; }
     double2 lg0 = make_double2(0.0, 0.0);
     for (int32_t ec = e0; ec < e1; ec += WAVE) {
         // this batch's source leaves and their ranges
@@ -246,16 +259,19 @@ __global__ void __launch_bounds__(256) k_p2l(const double4 *__restrict__ srcs,
         const int32_t ne = min(e1 - ec, WAVE);
         for (int32_t q = 0; q < ne; ++q) {
             const int32_t j0 = __builtin_amdgcn_readlane(mj0, q), j1 = __builtin_amdgcn_readlane(mj1, q);
-            for (int32_t j = j0 + r; j < j1; j += 16) {
+            for (int32_t j = j0 + r; j < j1; j += 32) {
                 const double4 d = srcs[j];
                 const double2 u = cinv_fast(make_double2(d.x - cx, d.y - cy));
-                double2 pw = cmul(make_double2(d.z, d.w), group_power(cpow_ct<KG>(u), g));
-                if (!LOG) pw = cmul(pw, u);
+                const double2 u2 = cmul(u, u);
+                // m u^g (LOG) or m u^(g+1)
+                const double2 m = make_double2(d.z, d.w);
+                const double2 mu = cmul(m, u);
+                double2 pw = LOG ? (g ? mu : m) : (g ? cmul(mu, u) : mu);
 #pragma unroll
-                for (int k = 0; k < KG; ++k) {
+                for (int k = 0; k < KT; ++k) {
                     sr[k] += pw.x;
                     si[k] += pw.y;
-                    if (k + 1 < KG) pw = cmul(pw, u);
+                    if (k + 1 < KT) pw = cmul(pw, u2);
                 }
             }
             if (LOG) {
@@ -276,9 +292,9 @@ __global__ void __launch_bounds__(256) k_p2l(const double4 *__restrict__ srcs,
         lg0.y = wave_sum(lg0.y);
     }
 #pragma unroll
-    for (int q = 0; q < KG; ++q) {
-        const double re = sum16_64(sr[q]), im = sum16_64(si[q]);
-        const int k = kb + q;
+    for (int q = 0; q < KT; ++q) {
+        const double re = sum32_64(sr[q]), im = sum32_64(si[q]);
+        const int k = g + 2 * q;
         if (r == 0 && k <= p) {
             double2 o = out[k];
             if (LOG) {
