@@ -539,6 +539,16 @@ __device__ __forceinline__ void m2l_finish16(const m2l_args &a, int kq, m2l_chun
     if (!c.valid) c.a0 = make_double2(0.0, 0.0);
 }
 
+// Rows 16 mt + 4 j + kq of an accumulator element exist only up to p <= 4 KS
+// (the instance's k-steps bound the order): in the shapes of up to two row
+// tiles the elements of higher rows are neither post-scaled, summed nor
+// written (in the 5-tile shape of p <= 64 skipping them raised the spills).
+template <int MT, int KS>
+__host__ __device__ constexpr bool m2l_row_live(int mt, int j)
+{
+    return MT > 2 || 16 * mt + 4 * j <= 4 * KS;
+}
+
 // One chunk of 16 weak pairs in FP64 with MTN row tiles and KSN k-steps
 // (the chunk's largest order qc needs rows 0..qc and a_1..a_qc).  Lane layout
 // of v_mfma_f64_16x16x4f64: A operand lane i holds A[i%16][i/16], B operand
@@ -592,6 +602,7 @@ __device__ __forceinline__ void m2l64_chunk(const double *Sl, const double *Il, 
         double2 v = u;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+            if (!m2l_row_live<MT, KS>(mt, j)) continue;
             const int row = 16 * mt + 4 * j + kq;
             double cr = Cr[mt][j], ci = Ci[mt][j];
             if (LOG) {
@@ -686,10 +697,11 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, const double *Sop, 
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            re[mt][j] = sum16_64(re[mt][j]);
-            im[mt][j] = sum16_64(im[mt][j]);
-        }
+        for (int j = 0; j < 4; ++j)
+            if (m2l_row_live<MT, KS>(mt, j)) {
+                re[mt][j] = sum16_64(re[mt][j]);
+                im[mt][j] = sum16_64(im[mt][j]);
+            }
 }
 
 // Waves per SIMD the register budget is sized for: three where the body fits
@@ -756,7 +768,8 @@ k_m2l64(m2l_args a, int32_t H)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int row = 16 * mt + 4 * j + kq;
-                    if (pr == 0 && row <= a.p) Bt[row] = make_double2(re[mt][j], im[mt][j]);
+                    if (m2l_row_live<MT, KS>(mt, j) && pr == 0 && row <= a.p)
+                        Bt[row] = make_double2(re[mt][j], im[mt][j]);
                 }
             return;
         }
@@ -764,7 +777,7 @@ k_m2l64(m2l_args a, int32_t H)
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (pr == 0) {
+                if (m2l_row_live<MT, KS>(mt, j) && pr == 0) {
                     part[w][16 * mt + 4 * j + kq][0] = re[mt][j];
                     part[w][16 * mt + 4 * j + kq][1] = im[mt][j];
                 }
