@@ -558,9 +558,13 @@ __host__ __device__ constexpr bool m2l_row_live(int mt, int j)
 // whole complex numbers of its pair and needs no lane exchange before the
 // post-scaling.  Straight-line code for each (MTN, KSN): the accumulators are
 // never merged across skipped products.
-template <int MT, int KS, int MTN, int KSN, bool LOG>
+struct m2l_no_hook {
+    __device__ void operator()() const {}
+};
+template <int MT, int KS, int MTN, int KSN, bool LOG, typename HOOK = m2l_no_hook>
 __device__ __forceinline__ void m2l64_chunk(const double *Sl, const double *Il, const m2l_chunk16<KS> &c,
-                                            double2 cT, int kq, double (&re)[MT][4], double (&im)[MT][4])
+                                            double2 cT, int kq, double (&re)[MT][4], double (&im)[MT][4],
+                                            HOOK hook = HOOK())
 {
     const int qlim = c.q; // rows above the pair's order are dropped (-1: no pair)
     const double2 r = make_double2(c.cS.x - cT.x, c.cS.y - cT.y);
@@ -594,6 +598,9 @@ __device__ __forceinline__ void m2l64_chunk(const double *Sl, const double *Il, 
             Cr[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, bre[ks], Cr[mt], 0, 0, 0);
             Ci[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, bim[ks], Ci[mt], 0, 0, 0);
         }
+    // the products are issued: the hook (the next chunk's loads) runs while
+    // they complete, in the registers of the operands no longer needed
+    hook();
     // Post-scale: row l = 16 mt + 4 j + kq gets r^{-l} (B_l - a_0/l); the
     // power starts at r^{-kq} and advances by r^-4 per row, r^-16 per tile.
     double2 u = kq == 0 ? make_double2(1.0, 0.0) : (kq == 1 ? r1 : (kq == 2 ? r2 : r3)); // r^{-kq}
@@ -680,7 +687,33 @@ __device__ __forceinline__ void m2l64_acc(const m2l_args &a, const double *Sop, 
     const int32_t *wl = a.sw ? a.sw : a.widx;
     const int32_t step = 16 * nw;
     int32_t e = e0 + 16 * w;
-    if (e < e1) {
+    // the shapes of p <= 20 hold the next chunk's operands without spills
+    constexpr bool PIPE = MT <= 2 && KS <= 5;
+    if (PIPE && e < e1 && !a.sp) {
+        // fixed order: every chunk takes the full body, and the next chunk's
+        // loads are issued once this chunk's products are (m2l64_chunk's hook)
+        int32_t sb1 = (e + step + pr < e1) ? wl[e + step + pr] : 0;
+        m2l_chunk16<KS> cur, nxt;
+        m2l_issue16<KS, LOG>(a, bo, nbl, e, e1, (e + pr < e1) ? wl[e + pr] : 0, pr, kq, cur);
+        int32_t sb0 = sb1;
+        sb1 = (e + 2 * step + pr < e1) ? wl[e + 2 * step + pr] : 0;
+        m2l_finish16<KS, LOG>(a, kq, cur);
+        for (; e < e1; e += step) {
+            const int32_t en = e + step;
+            const bool more = en < e1;
+            m2l64_chunk<MT, KS, MT, KS, LOG>(Sl, Il, cur, cT, kq, re, im, [&]() {
+                if (more) {
+                    m2l_issue16<KS, LOG>(a, bo, nbl, en, e1, sb0, pr, kq, nxt);
+                    sb0 = sb1;
+                    sb1 = (en + 2 * step + pr < e1) ? wl[en + 2 * step + pr] : 0;
+                }
+            });
+            if (more) {
+                m2l_finish16<KS, LOG>(a, kq, nxt);
+                cur = nxt;
+            }
+        }
+    } else if (e < e1) {
         int32_t sb1 = (e + step + pr < e1) ? wl[e + step + pr] : 0;
         int32_t sb0 = (e + pr < e1) ? wl[e + pr] : 0;
         for (; e < e1; e += step) {
