@@ -15,9 +15,11 @@
 //   b_l      += r^{-l} (B_l - a_0/l)       (l >= 1),   b_0 += B_0 + a_0 Log(c_T - c_S)
 // which is the re-expansion of (z-c_S)^{-k} and log(z-c_S) about c_T.  (The
 // printed listing of the M2L algorithm has sign slips; this is the operator
-// it describes.)  S is the same for every pair, so it stays in registers as
-// the MFMA A operand while the pre-scaled multipoles of 8 pairs (16 real
-// columns: re/im) stream through the B operand.
+// it describes.)  S is the same for every pair, so it is the MFMA A operand
+// (read from a table in LDS) while the pre-scaled multipoles stream through the
+// B operand: in FP64 (k_m2l64, v_mfma_f64_16x16x4f64) 16 pairs per chunk with
+// the real and imaginary parts in two accumulators; in FP32 (k_m2l32, the mixed
+// path, S in registers) 8 pairs per chunk as 16 real columns (re/im).
 #include <string.h>
 
 #include "common.h"
