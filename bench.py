@@ -65,6 +65,27 @@ def near_flops(st, n, p):
     return 16.0 * st["n_p2p_pairs"] + 8.0 * p * st["n_m2p_evals"]
 
 
+HBM_PEAK = 8000.0    # GB/s, MI355X HBM3E
+SUBTREE_MAX = 2048   # sources of a segment that the LDS subtree finishes
+
+
+def tree_bytes(n, L):
+    """Algorithmic HBM bytes of the tree phase at the sources (n points, depth
+    L), as its kernels are built: per point and axis the presort moves 296 B
+    (key init: the coordinate read, 8-byte key and 4-byte index written, 20 B;
+    8 radix passes of a histogram read of the key, 8 B, and a scatter that
+    reads and writes key and index, 24 B; the rank written by the last pass,
+    4 B; the decode, sorted key read and coordinate written, 16 B); the rank
+    records 32 B (four 4-byte ranks and orders read, two 8-byte records
+    written); every global split step 24 B (the record list read by the count
+    pass and read and written by the place pass); the LDS subtree 84 B (two
+    records read, the leaf order written, the source's coordinates and
+    strength gathered and written in leaf order, 4 + 2 x 32 B).  A split step
+    is global while a segment holds more than SUBTREE_MAX points."""
+    steps = sum(1 for s in range(2 * L) if -(-n // (1 << s)) > SUBTREE_MAX)
+    return n * (2 * 296 + 32 + 24 * steps + 84), steps
+
+
 def traffic_bytes():
     """HBM bytes per launch of the near-field kernel from the committed
     rocprofv3 counter summary, or None when the kernel source changed since
@@ -496,6 +517,13 @@ def main():
                      "kernel": "k_near (P2P + M2P, FP64)", "flops_per_launch": flops,
                      "avg_launch_ms": p2p_ms},
     }
+    tb, tsteps = tree_bytes(n, L)
+    tree_ms = head["phases"]["tree"]
+    line["tree_hbm"] = {"achieved": tb / (tree_ms * 1e-3) / 1e9, "peak": HBM_PEAK, "unit": "GB/s",
+                        "frac": tb / (tree_ms * 1e-3) / 1e9 / HBM_PEAK, "algorithmic_bytes": tb,
+                        "global_split_steps": tsteps, "ms": tree_ms,
+                        "note": "presort (both axes), rank records, global split steps and LDS subtree: "
+                                "algorithmic bytes over the tree phase time of the one-stream phase steps"}
     progress("steps with host copies")
     line["ms_per_step_with_copies"] = with_copies(f, fmm2d, src, m, args.p, max(3, args.steps // 2),
                                                   spec[chosen] + (chosen == "mutual",))
