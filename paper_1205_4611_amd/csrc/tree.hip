@@ -23,6 +23,15 @@
 //    the source splits by one pass per step (k_part_lb, decoupled look-back).
 //  * the tree is a pyramid with children 4b..4b+3, so segment j of split step
 //    k becomes segments 2j, 2j+1 of step k+1 and no host round-trip is needed.
+// Kernels: the presort is k_rs_init (keys), then per 8-bit digit k_rs_hist
+// (tile histograms), k_rs_colscan (per-digit scan over the tiles and the
+// digit totals) and k_rs_scatter (stable, staged through LDS, tiles in an
+// XCD-aware order; the last pass also writes every point's rank), then
+// k_rs_decode (the sorted coordinates); k_srec_init builds the rank records; a
+// global split step is k_seg (pivots and geometry of every segment) and
+// k_part_src count / place (the list across the split); k_subtree finishes
+// the segments in LDS; k_lists<false> counts and, after a scan of the counts,
+// k_lists<true> writes the interaction lists of one level.
 #pragma clang fp contract(off)
 
 #include <string.h>
